@@ -1,0 +1,315 @@
+/*
+ * ann.h -- C interface of the MI355X (gfx950) batched HNSW search library.
+ *
+ * The library answers k-nearest-neighbour queries over a dataset of
+ * d-dimensional vectors (arXiv 2501.06121, Section 1) with the HNSW index
+ * (Section 2: "The indexing method currently implemented ... is HNSW"):
+ * a greedy descent through the upper layers, then an ef-wide beam search on
+ * layer 0, over one of these representations:
+ *   - dense FP32 rows (the Identity quantizer, Section 2), or FP16, BF16 or
+ *     FP8-E4M3 (per-row scale) storage copies, with FP32 arithmetic;
+ *   - Product Quantization codes with asymmetric distances from per-query
+ *     lookup tables (Section 2: "Product Quantization");
+ *   - sparse vectors (Section 3, Table 1: the sparse dataset, inner product).
+ * The graph is always one built on the original vectors (Section 3.1,
+ * "Performance": the graph is built on the original representations, not on
+ * the quantized ones); the library only searches it.
+ *
+ * Keys ("distances", smaller is better): squared L2, or the negated inner
+ * product.  Ties are broken by the id: results are ordered by (key, id).
+ *
+ * Arithmetic order.  Every key is evaluated in one fixed FP32 order, so a
+ * result does not depend on the launch shape: 64 partial sums start at +0;
+ * element i belongs to chunk i / c (c = 16 bytes / element size: FP32 4,
+ * FP16 and BF16 8, FP8 16; sparse: c = 1 over the document's stored
+ * positions); chunk g feeds partial g mod 64 with one fused multiply-add per
+ * element in ascending i (L2: the difference is rounded first, then squared
+ * by the fma); the partials are then folded as p[l] += p[l ^ s] for
+ * s = 32, 16, 8, 4, 2, 1 and the key is +-p[0].  PQ: each lookup-table entry
+ * is one ascending fma chain over its subvector, and the per-subspace entries
+ * are folded by the same tree.  FP8: the IP key is -(scale * p[0]); the L2
+ * key squares q_i - fl(scale * x_i).
+ *
+ * Conventions for every entry point:
+ *   - Return value: ANN_OK (0) or one of the ANN_E* codes; the text of the
+ *     last error of the calling thread is in ann_last_error().
+ *   - Pointers documented as "device" are HIP device pointers (for example
+ *     torch tensor data pointers); "host" pointers are ordinary memory.  The
+ *     library never keeps a caller pointer after a call returns, except that
+ *     asynchronous calls read and write the device buffers until the stream
+ *     reaches the call's completion.
+ *   - nq == 0 is a successful no-op.  Invalid arguments are detected on the
+ *     host before anything is launched.
+ */
+#ifndef ANN_H_
+#define ANN_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define ANN_OK 0
+#define ANN_EINVAL 1   /* bad argument: null pointer, k < 1, ef < 1, sizes */
+#define ANN_ENODEV 2   /* no usable GPU / bad device ordinal */
+#define ANN_ENOMEM 3   /* device allocation failed */
+#define ANN_EBUDGET 4  /* request beyond a compiled or configured capacity */
+#define ANN_EFORMAT 5  /* malformed index description (graph or arrays) */
+#define ANN_EHIP 6     /* HIP runtime error; text in ann_last_error() */
+#define ANN_EUNSUP 7   /* the index lacks the arrays the requested mode needs */
+#define ANN_EAGAIN 8   /* serving queue full, try again later */
+
+/* ---- enums ------------------------------------------------------------- */
+enum ann_metric { ANN_METRIC_L2 = 0, ANN_METRIC_IP = 1 };
+
+enum ann_mode {
+  ANN_MODE_F32 = 0,    /* FP32 rows */
+  ANN_MODE_F16 = 1,    /* FP16 rows, FP32 arithmetic */
+  ANN_MODE_BF16 = 2,   /* BF16 rows, FP32 arithmetic */
+  ANN_MODE_FP8 = 3,    /* OCP E4M3 rows with one FP32 scale per row */
+  ANN_MODE_PQ = 4,     /* PQ codes, per-query lookup tables */
+  ANN_MODE_SPARSE = 5  /* sparse rows (CSR), inner product */
+};
+
+/* Largest ef (after ef_eff = max(ef, k)) one search can use: the beam lives
+ * in on-chip memory.  Larger requests fail with ANN_EBUDGET. */
+#define ANN_EF_MAX 4096
+/* Largest k and largest rerank depth. */
+#define ANN_K_MAX 1024
+
+/* ---- index ------------------------------------------------------------- */
+
+/*
+ * Everything the library needs to search, as HOST arrays.  The library
+ * copies them to the device at ann_index_create(); the caller may free them
+ * afterwards.  Arrays a mode does not use may be NULL.
+ *
+ * Graph (HNSW, Section 2 and its citation): n nodes, level[v] in 0..max_level,
+ * layer 0 lists of at most M0 ids, upper-layer lists of at most M ids.
+ *   levels      u8[n]
+ *   adj0        i32[n][M0]   layer-0 neighbours, valid ids first, then -1
+ *   upper_off   i32[n]       for level[v] >= 1: index (in lists) of v's
+ *                            level-1 list in upper_adj, its levels 2..level[v]
+ *                            lists follow; -1 for level-0 nodes
+ *   upper_adj   i32[n_upper_lists][M]   -1 padded
+ *   entry_point the node searched first, level[entry_point] == max_level
+ * Dense rows (row-major, n x d; d a multiple of 16):
+ *   x_f32 f32, x_f16 / x_bf16 u16 bit patterns, x_fp8 u8 E4M3 codes with
+ *   fp8_scale f32[n].
+ * PQ (pq_m subspaces of d / pq_m contiguous dimensions, 256 centroids):
+ *   pq_codebook f32[pq_m][256][d / pq_m], pq_codes u8[n][pq_m]; pq_m <= 64.
+ * Sparse (CSR over a vocabulary of `d` terms, ids strictly increasing per row):
+ *   sp_indptr i64[n + 1], sp_ids u16[nnz], sp_vals f32[nnz].
+ */
+typedef struct ann_index_desc {
+  int64_t n;
+  int32_t d;
+  int32_t metric;       /* enum ann_metric; sparse requires ANN_METRIC_IP */
+  int32_t M;
+  int32_t M0;           /* <= 64 */
+  int32_t max_level;
+  int32_t entry_point;
+  int64_t n_upper_lists;
+  const uint8_t* levels;
+  const int32_t* adj0;
+  const int32_t* upper_off;
+  const int32_t* upper_adj;
+  const float* x_f32;
+  const uint16_t* x_f16;
+  const uint16_t* x_bf16;
+  const uint8_t* x_fp8;
+  const float* fp8_scale;
+  int32_t pq_m;
+  int32_t pq_ksub;      /* must be 256 when PQ arrays are given */
+  const float* pq_codebook;
+  const uint8_t* pq_codes;
+  const int64_t* sp_indptr;
+  const uint16_t* sp_ids;
+  const float* sp_vals;
+} ann_index_desc;
+
+typedef struct ann_index ann_index; /* opaque, device-resident */
+
+/* Validates `desc`, allocates device memory on GPU `device`, copies every
+ * given array and returns the handle in *out.  The graph is checked on the
+ * host (ids in range, lists -1 padded, entry point at max_level):
+ * ANN_EFORMAT if not.  ANN_ENOMEM if the device is out of memory. */
+int ann_index_create(const ann_index_desc* desc, int device, ann_index** out);
+
+/* Frees the index and its device memory (waits for the device first). */
+int ann_index_free(ann_index* ix);
+
+typedef struct ann_index_info {
+  int64_t n;
+  int32_t d, metric, M, M0, max_level, entry_point;
+  int32_t modes;       /* bit (1 << mode) set for every searchable mode */
+  int32_t device;
+  int64_t device_bytes;
+} ann_index_info;
+
+int ann_index_info_get(const ann_index* ix, ann_index_info* out);
+
+/* ---- search ------------------------------------------------------------ */
+
+/*
+ * HNSW search (the citation's Algorithm 5: greedy descent on layers
+ * max_level..1, then the ef-wide beam on layer 0), FP32 rows, one k and one
+ * ef for every query, on the index's own stream; returns when done.
+ *   queries    device f32[nq][d]
+ *   out_ids    device i64[nq][k]   ascending (key, id); -1 when fewer than k
+ *                                  nodes were reached
+ *   out_dists  device f32[nq][k]   the keys; +inf with id -1
+ * ef_eff = max(ef, k) must not exceed ANN_EF_MAX (ANN_EBUDGET).
+ */
+int ann_search(const ann_index* ix, const float* queries, int64_t nq, int32_t k, int32_t ef,
+               int64_t* out_ids, float* out_dists);
+
+/*
+ * A batch with per-query k and ef, a representation and an optional exact
+ * rerank, asynchronous on `stream` (a hipStream_t; NULL = the index's own
+ * stream, and then the call waits for completion).
+ *
+ *   mode           enum ann_mode of the traversal keys
+ *   rerank         R >= 0.  If R > 0, the first R_eff = min(max(R, k), |W|)
+ *                  entries of the final layer-0 beam W are re-scored with the
+ *                  FP32 rows in the fixed FP32 order above, re-sorted by
+ *                  (key, id) and the first k returned.  Needs x_f32.
+ *   queries        device f32[nq][d] (dense and PQ modes)
+ *   q_indptr, q_ids, q_vals   device CSR of the sparse queries (sparse mode):
+ *                  i64[nq + 1], u16, f32; ids strictly increasing per query,
+ *                  at most 256 nonzeros per query
+ *   k, ef          device i32[nq] per-query values, or NULL to use k_all /
+ *                  ef_all for every query
+ *   k_max, ef_max  host-side upper bounds of the per-query values (they size
+ *                  on-chip memory and the output rows); a query whose k or ef
+ *                  exceeds them is clamped and flagged in out_status
+ *   out_ids        device i64[nq][k_max]; columns >= k of a row are -1
+ *   out_dists      device f32[nq][k_max]; +inf where the id is -1
+ *   out_status     optional device i32[nq]: 0 = ok, 1 = k or ef clamped
+ *   out_stats      optional device i32[nq][4]: distance evaluations (all
+ *                  layers), layer-0 expansions, layer-0 visited count, |W|
+ *   out_visited    optional device i32[nq][visited_cap]: the layer-0 visited
+ *                  ids in the order they were first reached (-1 padded,
+ *                  truncated to visited_cap); for testing
+ */
+typedef struct ann_batch {
+  int32_t mode;
+  int32_t rerank;
+  int64_t nq;
+  const float* queries;
+  const int64_t* q_indptr;
+  const uint16_t* q_ids;
+  const float* q_vals;
+  const int32_t* k;
+  const int32_t* ef;
+  int32_t k_all, ef_all;
+  int32_t k_max, ef_max;
+  int64_t* out_ids;
+  float* out_dists;
+  int32_t* out_status;
+  int32_t* out_stats;
+  int32_t* out_visited;
+  int64_t visited_cap;
+} ann_batch;
+
+int ann_search_ex(const ann_index* ix, const ann_batch* b, void* stream);
+
+/* Sparse convenience form of ann_search_ex (mode ANN_MODE_SPARSE), blocking. */
+int ann_search_sparse(const ann_index* ix, const int64_t* q_indptr, const uint16_t* q_ids,
+                      const float* q_vals, int64_t nq, int32_t k, int32_t ef,
+                      int64_t* out_ids, float* out_dists);
+
+/* ---- launch configuration ------------------------------------------------ */
+
+/*
+ * The traversal kernel is persistent: `slots` one-wavefront workgroups pull
+ * query indices from a device counter.  lanes_per_row (16, 32 or 64) is how
+ * many lanes evaluate one dense row together.  Zeros select the built-in
+ * defaults (or the autotuned values, once ann_autotune has run).
+ */
+typedef struct ann_launch_cfg {
+  int32_t slots;
+  int32_t lanes_per_row;
+} ann_launch_cfg;
+
+int ann_set_launch(ann_index* ix, int32_t mode, const ann_launch_cfg* cfg);
+int ann_get_launch(const ann_index* ix, int32_t mode, ann_launch_cfg* out);
+
+/*
+ * Times the candidate launch shapes on the given batch (device queries, as in
+ * ann_search_ex) and keeps the fastest for `mode`.  Results are identical for
+ * every shape (the arithmetic order is fixed); only speed differs.  The chosen
+ * configuration is written to *best when not NULL.
+ */
+int ann_autotune(ann_index* ix, const ann_batch* b, ann_launch_cfg* best);
+
+/* ---- exact search on matrix cores ---------------------------------------- */
+
+/*
+ * Brute-force k-NN over all FP32 rows with matrix-core (MFMA) tiles of
+ * Q x X^T followed by an exact FP32 re-score of the preselected candidates
+ * in the fixed order above.  queries device f32[nq][d]; out_ids/out_dists
+ * device [nq][k], ascending (key, id).  k <= 128.  Asynchronous on `stream`
+ * (NULL: index stream, blocking).
+ */
+int ann_bruteforce(const ann_index* ix, const float* queries, int64_t nq, int32_t k,
+                   int64_t* out_ids, float* out_dists, void* stream);
+
+/* ---- serving: continuous batching ------------------------------------------ */
+
+typedef struct ann_server ann_server;
+
+typedef struct ann_server_cfg {
+  int32_t mode;          /* enum ann_mode (dense modes) */
+  int32_t rerank;        /* as in ann_batch */
+  int32_t max_inflight;  /* queries on the device at once (slots), > 0 */
+  int32_t max_batch;     /* largest batch one launch takes, > 0 */
+  int32_t streams;       /* concurrent launches (1..4) */
+  int32_t k_max;         /* upper bound of request k, <= ANN_K_MAX */
+  int32_t ef_max;        /* upper bound of request ef, <= ANN_EF_MAX */
+  int32_t queue_cap;     /* waiting requests before ANN_EAGAIN */
+  int64_t hbm_budget;    /* bytes of device memory the server may use */
+} ann_server_cfg;
+
+typedef struct ann_request {
+  uint64_t tag;          /* returned in the completion */
+  const float* query;    /* host f32[d]; copied at submit */
+  int32_t k, ef;
+} ann_request;
+
+typedef struct ann_completion {
+  uint64_t tag;
+  int32_t status;        /* ANN_OK or an error code */
+  int32_t k;
+  int64_t ids[ANN_K_MAX];
+  float dists[ANN_K_MAX];
+  double t_submit, t_start, t_done;  /* seconds, steady clock */
+} ann_completion;
+
+/* Starts a server thread that admits queued requests into free slots while
+ * earlier batches still run, launching each admitted batch on its own stream. */
+int ann_server_create(const ann_index* ix, const ann_server_cfg* cfg, ann_server** out);
+/* Copies the request into the queue; ANN_EAGAIN if the queue is full. */
+int ann_server_submit(ann_server* s, const ann_request* r);
+/* Moves up to `max` finished requests into out[]; returns how many (>= 0),
+ * or a negative error code.  Non-blocking. */
+int ann_server_poll(ann_server* s, ann_completion* out, int32_t max);
+/* Stops admitting, drains in-flight work, joins the thread, frees memory. */
+int ann_server_destroy(ann_server* s);
+
+/* ---- misc -------------------------------------------------------------- */
+
+/* Text of the calling thread's last error ("" if none). */
+const char* ann_last_error(void);
+/* Library version, e.g. 1. */
+int ann_version(void);
+/* Number of visible GPUs (0 if none); does not fail. */
+int ann_device_count(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ANN_H_ */

@@ -1,0 +1,408 @@
+"""Python binding of libann.so, the MI355X batched HNSW search library.
+
+Argument marshalling only: every step of a search runs in the library's HIP
+kernels (see include/ann.h for the operations and their conventions).  Torch
+is used for device memory and streams.  The functions carry the names of the
+C entry points.
+
+The library must have been built (``python -m paper_2501_06121_amd.build``);
+importing a function that needs it raises if ``libann.so`` is missing: there
+is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libann.so")
+
+ANN_OK, ANN_EINVAL, ANN_ENODEV, ANN_ENOMEM, ANN_EBUDGET, ANN_EFORMAT, ANN_EHIP, ANN_EUNSUP, \
+    ANN_EAGAIN = range(9)
+ERR_NAMES = {0: "ANN_OK", 1: "ANN_EINVAL", 2: "ANN_ENODEV", 3: "ANN_ENOMEM", 4: "ANN_EBUDGET",
+             5: "ANN_EFORMAT", 6: "ANN_EHIP", 7: "ANN_EUNSUP", 8: "ANN_EAGAIN"}
+METRIC = {"l2": 0, "ip": 1}
+MODE = {"f32": 0, "f16": 1, "bf16": 2, "fp8": 3, "pq": 4, "sparse": 5}
+ANN_EF_MAX = 4096
+ANN_K_MAX = 1024
+
+P = C.c_void_p
+I32, I64, U64, F64 = C.c_int32, C.c_int64, C.c_uint64, C.c_double
+
+
+class AnnIndexDesc(C.Structure):
+    _fields_ = [("n", I64), ("d", I32), ("metric", I32), ("M", I32), ("M0", I32),
+                ("max_level", I32), ("entry_point", I32), ("n_upper_lists", I64),
+                ("levels", P), ("adj0", P), ("upper_off", P), ("upper_adj", P),
+                ("x_f32", P), ("x_f16", P), ("x_bf16", P), ("x_fp8", P), ("fp8_scale", P),
+                ("pq_m", I32), ("pq_ksub", I32), ("pq_codebook", P), ("pq_codes", P),
+                ("sp_indptr", P), ("sp_ids", P), ("sp_vals", P)]
+
+
+class AnnIndexInfo(C.Structure):
+    _fields_ = [("n", I64), ("d", I32), ("metric", I32), ("M", I32), ("M0", I32),
+                ("max_level", I32), ("entry_point", I32), ("modes", I32), ("device", I32),
+                ("device_bytes", I64)]
+
+
+class AnnBatch(C.Structure):
+    _fields_ = [("mode", I32), ("rerank", I32), ("nq", I64),
+                ("queries", P), ("q_indptr", P), ("q_ids", P), ("q_vals", P),
+                ("k", P), ("ef", P), ("k_all", I32), ("ef_all", I32), ("k_max", I32),
+                ("ef_max", I32), ("out_ids", P), ("out_dists", P), ("out_status", P),
+                ("out_stats", P), ("out_visited", P), ("visited_cap", I64)]
+
+
+class AnnLaunchCfg(C.Structure):
+    _fields_ = [("slots", I32), ("lanes_per_row", I32)]
+
+
+class AnnServerCfg(C.Structure):
+    _fields_ = [("mode", I32), ("rerank", I32), ("max_inflight", I32), ("max_batch", I32),
+                ("streams", I32), ("k_max", I32), ("ef_max", I32), ("queue_cap", I32),
+                ("hbm_budget", I64)]
+
+
+class AnnRequest(C.Structure):
+    _fields_ = [("tag", U64), ("query", P), ("k", I32), ("ef", I32)]
+
+
+class AnnCompletion(C.Structure):
+    _fields_ = [("tag", U64), ("status", I32), ("k", I32), ("ids", I64 * ANN_K_MAX),
+                ("dists", C.c_float * ANN_K_MAX), ("t_submit", F64), ("t_start", F64),
+                ("t_done", F64)]
+
+
+# Every exported symbol and its argument types; the CPU tests check that the
+# library exports all of them.
+SIGNATURES = {
+    "ann_index_create": ([P, C.c_int, P], C.c_int),
+    "ann_index_free": ([P], C.c_int),
+    "ann_index_info_get": ([P, P], C.c_int),
+    "ann_search": ([P, P, I64, I32, I32, P, P], C.c_int),
+    "ann_search_ex": ([P, P, P], C.c_int),
+    "ann_search_sparse": ([P, P, P, P, I64, I32, I32, P, P], C.c_int),
+    "ann_set_launch": ([P, I32, P], C.c_int),
+    "ann_get_launch": ([P, I32, P], C.c_int),
+    "ann_autotune": ([P, P, P], C.c_int),
+    "ann_bruteforce": ([P, P, I64, I32, P, P, P], C.c_int),
+    "ann_server_create": ([P, P, P], C.c_int),
+    "ann_server_submit": ([P, P], C.c_int),
+    "ann_server_poll": ([P, P, I32], C.c_int),
+    "ann_server_destroy": ([P], C.c_int),
+    "ann_last_error": ([], C.c_char_p),
+    "ann_version": ([], C.c_int),
+    "ann_device_count": ([], C.c_int),
+}
+
+_lib = None
+
+
+def _load_hip_runtime():
+    """Load the HIP runtime PyTorch uses before the library.
+
+    The library was linked against that runtime; loading it first makes the
+    library bind to the same copy (matched by its soname), so that torch and
+    the library share one runtime and one view of the GPU.
+    """
+    try:
+        import torch
+    except ImportError:
+        return
+    rt = os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so")
+    if os.path.exists(rt):
+        C.CDLL(rt, mode=getattr(os, "RTLD_GLOBAL", 0x100))
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2501_06121_amd.build` (no fallback exists)")
+        _load_hip_runtime()
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+class AnnError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != ANN_OK:
+        raise AnnError(rc, lib().ann_last_error().decode())
+    return rc
+
+
+def _np(a, dtype):
+    return None if a is None else np.ascontiguousarray(a, dtype=dtype)
+
+
+def _hptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _dptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+# --------------------------------------------------------------------------
+# index
+# --------------------------------------------------------------------------
+
+class Index:
+    """Owns an ann_index handle; freed with ann_index_free on close/GC."""
+
+    def __init__(self, handle, d, metric):
+        self.handle = handle
+        self.d = d
+        self.metric = metric
+
+    def close(self):
+        if self.handle:
+            lib().ann_index_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        out = AnnIndexInfo()
+        _check(lib().ann_index_info_get(self.handle, C.byref(out)))
+        return {f: getattr(out, f) for f, _ in AnnIndexInfo._fields_}
+
+
+def ann_index_create(graph, metric, d, x_f32=None, x_f16=None, x_bf16=None, x_fp8=None,
+                     fp8_scale=None, pq_codebook=None, pq_codes=None, sp_indptr=None,
+                     sp_ids=None, sp_vals=None, device=0):
+    """Copy host arrays to the device.  `graph` has the attributes n, M, M0,
+    max_level, entry, levels, adj0, upper_off, upper_adj (exchange layout)."""
+    keep = dict(levels=_np(graph.levels, np.uint8), adj0=_np(graph.adj0, np.int32),
+                upper_off=_np(graph.upper_off, np.int32), upper_adj=_np(graph.upper_adj, np.int32),
+                x_f32=_np(x_f32, np.float32), x_f16=_np(x_f16, np.uint16),
+                x_bf16=_np(x_bf16, np.uint16), x_fp8=_np(x_fp8, np.uint8),
+                fp8_scale=_np(fp8_scale, np.float32), pq_codebook=_np(pq_codebook, np.float32),
+                pq_codes=_np(pq_codes, np.uint8), sp_indptr=_np(sp_indptr, np.int64),
+                sp_ids=_np(sp_ids, np.uint16), sp_vals=_np(sp_vals, np.float32))
+    D = AnnIndexDesc()
+    D.n, D.d, D.metric = int(graph.n), int(d), METRIC[metric]
+    D.M, D.M0, D.max_level, D.entry_point = int(graph.M), int(graph.M0), int(graph.max_level), int(graph.entry)
+    D.n_upper_lists = int(keep["upper_adj"].size // max(1, int(graph.M)))
+    for k, v in keep.items():
+        setattr(D, k, _hptr(v))
+    if keep["pq_codes"] is not None:
+        D.pq_m = int(keep["pq_codes"].shape[1])
+        D.pq_ksub = int(keep["pq_codebook"].shape[1])
+    h = P()
+    _check(lib().ann_index_create(C.byref(D), int(device), C.byref(h)))
+    return Index(h, int(d), metric)
+
+
+def ann_index_free(index):
+    index.close()
+
+
+# --------------------------------------------------------------------------
+# search
+# --------------------------------------------------------------------------
+
+def ann_search(index, queries, k, ef):
+    """FP32 search, one k and ef; queries: cuda float32 [nq, d].  Blocking."""
+    torch = _torch()
+    nq = queries.shape[0]
+    ids = torch.empty((nq, k), dtype=torch.int64, device=queries.device)
+    dists = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
+    _check(lib().ann_search(index.handle, _dptr(queries), nq, int(k), int(ef), _dptr(ids),
+                            _dptr(dists)))
+    return ids, dists
+
+
+def ann_search_ex(index, mode="f32", queries=None, sparse=None, k=10, ef=64, rerank=0,
+                  k_max=None, ef_max=None, stream=None, want_stats=False, visited_cap=0,
+                  out=None):
+    """Batched search with per-query k/ef (ints or cuda int32 tensors).
+
+    sparse = (indptr i64, ids i16/i32->u16, vals f32) cuda tensors.  With
+    stream=None the call runs on the index stream and blocks; with a torch
+    stream it is asynchronous on that stream.  Returns a dict of tensors.
+    """
+    torch = _torch()
+    if sparse is not None:
+        q_ptr, q_ids, q_vals = sparse
+        nq = q_ptr.shape[0] - 1
+        dev = q_ptr.device
+    else:
+        nq = queries.shape[0]
+        dev = queries.device
+    b = AnnBatch()
+    b.mode = MODE[mode] if isinstance(mode, str) else int(mode)
+    b.rerank = int(rerank)
+    b.nq = nq
+    b.queries = _dptr(queries)
+    if sparse is not None:
+        b.q_indptr, b.q_ids, b.q_vals = _dptr(q_ptr), _dptr(q_ids), _dptr(q_vals)
+    if torch.is_tensor(k):
+        b.k = _dptr(k)
+        b.k_max = int(k_max if k_max is not None else int(k.max().item()) if nq else 1)
+    else:
+        b.k_all = int(k)
+        b.k_max = int(k_max if k_max is not None else k)
+    if torch.is_tensor(ef):
+        b.ef = _dptr(ef)
+        b.ef_max = int(ef_max if ef_max is not None else int(ef.max().item()) if nq else 1)
+    else:
+        b.ef_all = int(ef)
+        b.ef_max = int(ef_max if ef_max is not None else ef)
+    res = out or {}
+    if "ids" not in res:
+        res["ids"] = torch.empty((nq, b.k_max), dtype=torch.int64, device=dev)
+        res["dists"] = torch.empty((nq, b.k_max), dtype=torch.float32, device=dev)
+        res["status"] = torch.empty((nq,), dtype=torch.int32, device=dev)
+        if want_stats:
+            res["stats"] = torch.empty((nq, 4), dtype=torch.int32, device=dev)
+        if visited_cap:
+            res["visited"] = torch.empty((nq, visited_cap), dtype=torch.int32, device=dev)
+    b.out_ids, b.out_dists = _dptr(res["ids"]), _dptr(res["dists"])
+    b.out_status = _dptr(res.get("status"))
+    b.out_stats = _dptr(res.get("stats"))
+    if "visited" in res:
+        b.out_visited = _dptr(res["visited"])
+        b.visited_cap = res["visited"].shape[1]
+    _check(lib().ann_search_ex(index.handle, C.byref(b), _stream_handle(stream)))
+    return res
+
+
+def ann_search_sparse(index, indptr, ids, vals, k, ef):
+    torch = _torch()
+    nq = indptr.shape[0] - 1
+    out_ids = torch.empty((nq, k), dtype=torch.int64, device=indptr.device)
+    out_d = torch.empty((nq, k), dtype=torch.float32, device=indptr.device)
+    _check(lib().ann_search_sparse(index.handle, _dptr(indptr), _dptr(ids), _dptr(vals), nq,
+                                   int(k), int(ef), _dptr(out_ids), _dptr(out_d)))
+    return out_ids, out_d
+
+
+def ann_set_launch(index, mode, slots=0, lanes_per_row=0):
+    cfg = AnnLaunchCfg(int(slots), int(lanes_per_row))
+    _check(lib().ann_set_launch(index.handle, MODE[mode] if isinstance(mode, str) else int(mode),
+                                C.byref(cfg)))
+
+
+def ann_get_launch(index, mode):
+    cfg = AnnLaunchCfg()
+    _check(lib().ann_get_launch(index.handle, MODE[mode] if isinstance(mode, str) else int(mode),
+                                C.byref(cfg)))
+    return {"slots": cfg.slots, "lanes_per_row": cfg.lanes_per_row}
+
+
+def ann_autotune(index, mode="f32", queries=None, sparse=None, k=10, ef=64, rerank=0):
+    torch = _torch()
+    nq = queries.shape[0] if queries is not None else sparse[0].shape[0] - 1
+    dev = queries.device if queries is not None else sparse[0].device
+    ids = torch.empty((nq, k), dtype=torch.int64, device=dev)
+    dists = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    b = AnnBatch()
+    b.mode = MODE[mode]
+    b.rerank = int(rerank)
+    b.nq = nq
+    b.queries = _dptr(queries)
+    if sparse is not None:
+        b.q_indptr, b.q_ids, b.q_vals = (_dptr(t) for t in sparse)
+    b.k_all, b.k_max, b.ef_all, b.ef_max = int(k), int(k), int(ef), int(max(ef, k))
+    b.out_ids, b.out_dists = _dptr(ids), _dptr(dists)
+    cfg = AnnLaunchCfg()
+    _check(lib().ann_autotune(index.handle, C.byref(b), C.byref(cfg)))
+    return {"slots": cfg.slots, "lanes_per_row": cfg.lanes_per_row}
+
+
+def ann_bruteforce(index, queries, k, stream=None):
+    torch = _torch()
+    nq = queries.shape[0]
+    ids = torch.empty((nq, k), dtype=torch.int64, device=queries.device)
+    dists = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
+    _check(lib().ann_bruteforce(index.handle, _dptr(queries), nq, int(k), _dptr(ids), _dptr(dists),
+                                _stream_handle(stream)))
+    return ids, dists
+
+
+# --------------------------------------------------------------------------
+# serving
+# --------------------------------------------------------------------------
+
+class Server:
+    """Continuous-batching server around ann_server_* (host query vectors)."""
+
+    def __init__(self, index, mode="f16", rerank=0, max_inflight=4096, max_batch=1024,
+                 streams=2, k_max=100, ef_max=512, queue_cap=1 << 16, hbm_budget=8 << 30):
+        cfg = AnnServerCfg(MODE[mode], int(rerank), int(max_inflight), int(max_batch),
+                           int(streams), int(k_max), int(ef_max), int(queue_cap), int(hbm_budget))
+        self.index = index
+        self.handle = P()
+        _check(lib().ann_server_create(index.handle, C.byref(cfg), C.byref(self.handle)))
+        self._buf = (AnnCompletion * 256)()
+
+    def submit(self, tag, query, k, ef):
+        q = np.ascontiguousarray(query, dtype=np.float32)
+        r = AnnRequest(int(tag), q.ctypes.data, int(k), int(ef))
+        rc = lib().ann_server_submit(self.handle, C.byref(r))
+        if rc == ANN_EAGAIN:
+            return False
+        _check(rc)
+        return True
+
+    def poll(self):
+        n = lib().ann_server_poll(self.handle, self._buf, len(self._buf))
+        if n < 0:
+            _check(-n)
+        out = []
+        for i in range(n):
+            c = self._buf[i]
+            kk = c.k
+            out.append(dict(tag=c.tag, status=c.status, ids=np.array(c.ids[:kk], np.int64),
+                            dists=np.array(c.dists[:kk], np.float32), t_submit=c.t_submit,
+                            t_start=c.t_start, t_done=c.t_done))
+        return out
+
+    def close(self):
+        if self.handle:
+            _check(lib().ann_server_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ann_version():
+    return lib().ann_version()
+
+
+def ann_device_count():
+    return lib().ann_device_count()

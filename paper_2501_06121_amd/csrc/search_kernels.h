@@ -1,0 +1,66 @@
+// Internal interface between the C-ABI host code and the search kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ann {
+
+enum { MODE_F32 = 0, MODE_F16 = 1, MODE_BF16 = 2, MODE_FP8 = 3, MODE_PQ = 4, MODE_SPARSE = 5 };
+enum { METRIC_L2 = 0, METRIC_IP = 1 };
+
+struct SearchParams {
+  int mode, metric;
+  int d, nchunks, lanes_per_row;
+  // representation searched
+  const void* rows;
+  const float* fp8_scale;
+  const float* pq_cb;
+  const uint8_t* pq_codes;
+  int pq_m, pq_dsub, pq_stride;
+  const int64_t* sp_ptr;
+  const uint16_t* sp_ids;
+  const float* sp_vals;
+  const float* x_f32;               // rerank rows
+  // graph
+  int64_t n;
+  int M, M0, max_level, entry;
+  const int32_t* adj0;
+  const int32_t* upper_off;
+  const int32_t* upper_adj;
+  // batch
+  int64_t nq;
+  const float* queries;
+  const int64_t* q_ptr;
+  const uint16_t* q_ids;
+  const float* q_vals;
+  const int32_t* k_arr;
+  const int32_t* ef_arr;
+  int k_all, ef_all, k_max, ef_cap, rerank;
+  int q_lds_floats;
+  int64_t* out_ids;
+  float* out_dists;
+  int32_t* out_status;
+  int32_t* out_stats;
+  int32_t* out_visited;
+  int64_t visited_cap;
+  // workspace
+  uint32_t* bits;
+  int64_t bits_words;
+  int32_t* vlog;
+  int vlog_cap;
+  int32_t* counter;
+};
+
+hipError_t launch_search(const SearchParams& p, int slots, size_t lds, hipStream_t st);
+size_t lds_bytes(const SearchParams& p);
+const void* kernel_symbol(const SearchParams& p);
+bool dense_shape_supported(int mode, int nchunks, int lanes_per_row);
+
+// brute force on matrix cores
+hipError_t launch_bruteforce(const float* X, int64_t n, int d, int metric, const float* Q,
+                             int64_t nq, int k, int64_t* out_ids, float* out_dists,
+                             void* scratch, size_t scratch_bytes, hipStream_t st);
+size_t bruteforce_scratch_bytes(int64_t n, int64_t nq, int k);
+
+}  // namespace ann

@@ -1,0 +1,822 @@
+// Batched HNSW search on gfx950: one wavefront per query, persistent grid.
+//
+// What each wave does for one query (HNSW, the paper's index of Section 2 and
+// its citation's Algorithm 5):
+//   1. query prep: the query's chunks into registers (dense), the PQ lookup
+//      table into LDS, or the sparse query into an LDS hash table;
+//   2. greedy descent through layers max_level..1 (ef = 1);
+//   3. the layer-0 beam of width ef, kept as ONE sorted list W in LDS with an
+//      "expanded" bit per entry: repeatedly expand the best unexpanded entry,
+//      gather its neighbour list, drop visited ids (a per-slot bitset in HBM),
+//      gather and score the new rows, and merge them into W keeping the best
+//      ef.  Under the (key, id) total order this is the citation's
+//      Algorithm 2 with the candidate queue folded into W: the queue's minimum
+//      is W's best unexpanded entry until none is left, which is exactly when
+//      Algorithm 2 stops;
+//   4. optional exact FP32 re-score of the first R entries of W;
+//   5. the first k by (key, id) to the output rows.
+//
+// Every key uses the fixed FP32 order documented in include/ann.h, so the
+// visited sets, the beam and the output are independent of the launch shape.
+//
+// Memory layout in HBM (written once by ann_index_create):
+//   rows       n x d elements, row-major, 16-byte chunks
+//   adj0       n x M0 i32, -1 padded (one 256-byte line for M0 = 64)
+//   upper      per upper node, one M-wide list per level >= 1
+//   bits       per slot, ceil(n / 32) u32 visited words
+//   vlog       per slot, the ids set in `bits` (to clear them afterwards)
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "search_kernels.h"
+
+namespace ann {
+
+constexpr uint32_t kExpanded = 0x80000000u;
+constexpr uint32_t kIdMask = 0x7FFFFFFFu;
+constexpr int kHashSlots = 512;               // sparse query table (<= 256 terms)
+constexpr uint32_t kHashEmpty = 0xFFFFFFFFu;
+
+// ----------------------------------------------------------------------------
+// small helpers
+// ----------------------------------------------------------------------------
+
+__device__ __forceinline__ int lane_id() { return (int)threadIdx.x; }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int mbcnt(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// strict (key, id) order; -0 and +0 compare equal, as in IEEE
+__device__ __forceinline__ bool kid_lt(float ka, uint32_t ia, float kb, uint32_t ib) {
+  return ka < kb || (ka == kb && ia < ib);
+}
+
+__device__ __forceinline__ float f16_bits_to_f32(uint32_t h) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)h);
+}
+
+__device__ __forceinline__ float bf16_bits_to_f32(uint32_t h) {
+  return __uint_as_float(h << 16);
+}
+
+// OCP E4M3: exponent bias 7, 3 mantissa bits; subnormals are m * 2^-9.
+__device__ __forceinline__ float e4m3_bits_to_f32(uint32_t b) {
+  const uint32_t em = b & 0x7Fu;
+  const float mag = (em >= 8u) ? __uint_as_float((((em >> 3) + 120u) << 23) | ((em & 7u) << 20))
+                               : (float)em * 0x1p-9f;
+  return __uint_as_float(__float_as_uint(mag) | ((b & 0x80u) << 24));
+}
+
+// ----------------------------------------------------------------------------
+// shared-memory layout of one wave (dynamic LDS)
+// ----------------------------------------------------------------------------
+
+struct Lds {
+  float* wkey;       // [ef_cap]
+  uint32_t* wid;     // [ef_cap] id | kExpanded
+  int32_t* cid;      // [64] candidate ids of one expansion
+  float* ckey;       // [64] their keys
+  int32_t* rnk;      // [64] insertion ranks
+  float* q;          // [d_pad] FP32 query (rerank, PQ tables)
+  float* rk;         // [ef_cap] rerank keys
+  float* lut;        // [pq_m * 256] PQ lookup table
+  uint32_t* hkey;    // [kHashSlots] sparse query terms
+  float* hval;       // [kHashSlots]
+};
+
+__device__ Lds carve(char* base, const SearchParams& p) {
+  Lds s;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { char* r = base + off; off += (bytes + 15) & ~size_t(15); return r; };
+  s.wkey = (float*)take(sizeof(float) * p.ef_cap);
+  s.wid = (uint32_t*)take(sizeof(uint32_t) * p.ef_cap);
+  s.cid = (int32_t*)take(sizeof(int32_t) * 64);
+  s.ckey = (float*)take(sizeof(float) * 64);
+  s.rnk = (int32_t*)take(sizeof(int32_t) * 64);
+  s.q = (float*)take(sizeof(float) * p.q_lds_floats);
+  s.rk = (float*)take(sizeof(float) * (p.rerank > 0 ? p.ef_cap : 0));
+  s.lut = (float*)take(sizeof(float) * (p.mode == MODE_PQ ? p.pq_m * 256 : 0));
+  s.hkey = (uint32_t*)take(sizeof(uint32_t) * (p.mode == MODE_SPARSE ? kHashSlots : 0));
+  s.hval = (float*)take(sizeof(float) * (p.mode == MODE_SPARSE ? kHashSlots : 0));
+  return s;
+}
+
+// ----------------------------------------------------------------------------
+// dense rows: chunk = 16 bytes; lane j of an L-lane group takes chunks
+// g = j + L * t and feeds partial (g mod 64), held as virtual partial
+// v = t mod (64 / L) of the lane.
+// ----------------------------------------------------------------------------
+
+template <int MODE> struct ElemsPerChunk;
+template <> struct ElemsPerChunk<MODE_F32> { static constexpr int value = 4; };
+template <> struct ElemsPerChunk<MODE_F16> { static constexpr int value = 8; };
+template <> struct ElemsPerChunk<MODE_BF16> { static constexpr int value = 8; };
+template <> struct ElemsPerChunk<MODE_FP8> { static constexpr int value = 16; };
+
+template <int MODE>
+__device__ __forceinline__ float chunk_elem(const uint4& r, int e) {
+  const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+  if constexpr (MODE == MODE_F32) {
+    return __uint_as_float(w[e]);
+  } else if constexpr (MODE == MODE_F16) {
+    return f16_bits_to_f32((w[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+  } else if constexpr (MODE == MODE_BF16) {
+    return bf16_bits_to_f32((w[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+  } else {
+    return e4m3_bits_to_f32((w[e >> 2] >> (8 * (e & 3))) & 0xFFu);
+  }
+}
+
+// One chunk folded into an accumulator, elements in ascending order.
+template <int MODE, bool IP>
+__device__ __forceinline__ float fold_chunk(float acc, const uint4& raw, const float* qc, float scale) {
+  constexpr int C = ElemsPerChunk<MODE>::value;
+#pragma unroll
+  for (int e = 0; e < C; ++e) {
+    float x = chunk_elem<MODE>(raw, e);
+    if constexpr (IP) {
+      acc = __builtin_fmaf(qc[e], x, acc);
+    } else {
+      if constexpr (MODE == MODE_FP8) x = scale * x;
+      const float t = qc[e] - x;
+      acc = __builtin_fmaf(t, t, acc);
+    }
+  }
+  return acc;
+}
+
+// Dense scoring policy.  L lanes per row, CPL chunks per lane.
+template <int MODE, int L, int CPL>
+struct Dense {
+  static constexpr int C = ElemsPerChunk<MODE>::value;
+  static constexpr int G = 64 / L;          // rows per pass
+  static constexpr int V = 64 / L;          // virtual partials per lane
+  static constexpr int U = 8 / CPL;         // passes in flight (<= 32 VGPRs of rows)
+  float qreg[CPL][C];
+
+  __device__ bool prep(const SearchParams& p, const Lds& s, int64_t q) {
+    const int j = lane_id() & (L - 1);
+    const float* qrow = p.queries + (size_t)q * p.d;
+#pragma unroll
+    for (int t = 0; t < CPL; ++t) {
+      const int g = j + L * t;
+#pragma unroll
+      for (int e = 0; e < C; ++e) {
+        const int i = g * C + e;
+        qreg[t][e] = (g < p.nchunks) ? qrow[i] : 0.0f;
+      }
+    }
+    return true;
+  }
+
+  // keys of the m candidate ids in s.cid[] into s.ckey[]
+  template <bool IP>
+  __device__ void score_impl(const SearchParams& p, const Lds& s, int m) {
+    const int lane = lane_id();
+    const int j = lane & (L - 1);
+    const int grp = lane / L;
+    const size_t row_bytes = (size_t)p.nchunks * 16;
+    const char* rows = (const char*)p.rows;
+    for (int base = 0; base < m; base += G * U) {
+      uint4 raw[U][CPL];
+      int rid[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int ci = base + u * G + grp;
+        rid[u] = (ci < m) ? s.cid[ci] : -1;
+        const char* rp = rows + (size_t)(rid[u] < 0 ? 0 : rid[u]) * row_bytes;
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) {
+          const int g = j + L * t;
+          if (rid[u] >= 0 && g < p.nchunks)
+            raw[u][t] = *(const uint4*)(rp + (size_t)g * 16);
+          else
+            raw[u][t] = make_uint4(0u, 0u, 0u, 0u);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (base + u * G >= m) break;
+        const float scale = (MODE == MODE_FP8 && rid[u] >= 0) ? p.fp8_scale[rid[u]] : 1.0f;
+        float acc[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[v] = 0.0f;
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) {
+          const int g = j + L * t;
+          if (g < p.nchunks) acc[t % V] = fold_chunk<MODE, IP>(acc[t % V], raw[u][t], qreg[t], scale);
+        }
+        // tree levels s = 32 .. L inside the lane
+#pragma unroll
+        for (int h = V / 2; h >= 1; h >>= 1)
+#pragma unroll
+          for (int v = 0; v < h; ++v) acc[v] = acc[v] + acc[v + h];
+        float val = acc[0];
+        // levels s = L/2 .. 1 across the lanes of the group
+#pragma unroll
+        for (int sft = L / 2; sft >= 1; sft >>= 1) val = val + __shfl_down(val, sft, L);
+        const int ci = base + u * G + grp;
+        if (j == 0 && ci < m) {
+          float key;
+          if constexpr (IP) {
+            if constexpr (MODE == MODE_FP8) val = scale * val;
+            key = -val;
+          } else {
+            key = val;
+          }
+          s.ckey[ci] = key;
+        }
+      }
+    }
+  }
+
+  __device__ void score(const SearchParams& p, const Lds& s, int m) {
+    if (p.metric == METRIC_IP) score_impl<true>(p, s, m);
+    else score_impl<false>(p, s, m);
+  }
+};
+
+// ----------------------------------------------------------------------------
+// PQ asymmetric distance: LUT[m][j] in LDS, one lane per candidate.
+// ----------------------------------------------------------------------------
+
+struct PQ {
+  __device__ bool prep(const SearchParams& p, const Lds& s, int64_t q) {
+    const int lane = lane_id();
+    const int ds = p.pq_dsub;
+    const int entries = p.pq_m * 256;
+    const bool ip = p.metric == METRIC_IP;
+    for (int e = lane; e < entries; e += 64) {
+      const int m = e >> 8;
+      const float* c = p.pq_cb + (size_t)e * ds;
+      const float* qs = s.q + m * ds;
+      float acc = 0.0f;
+      for (int t = 0; t < ds; ++t) {
+        if (ip) {
+          acc = __builtin_fmaf(qs[t], c[t], acc);
+        } else {
+          const float u = qs[t] - c[t];
+          acc = __builtin_fmaf(u, u, acc);
+        }
+      }
+      s.lut[e] = acc;
+    }
+    __syncthreads();
+    return true;
+  }
+
+  __device__ void score(const SearchParams& p, const Lds& s, int m) {
+    const int lane = lane_id();
+    if (lane < m) {
+      const int64_t r = s.cid[lane];
+      const uint4* cp = (const uint4*)(p.pq_codes + (size_t)r * p.pq_stride);
+      float part[64];
+      uint4 w4[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) w4[b] = (b * 16 < p.pq_m) ? cp[b] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+      for (int mm = 0; mm < 64; ++mm) {
+        const uint4 w = w4[mm >> 4];
+        const uint32_t word = ((mm >> 2) & 3) == 0 ? w.x : ((mm >> 2) & 3) == 1 ? w.y
+                              : ((mm >> 2) & 3) == 2 ? w.z : w.w;
+        const uint32_t code = (word >> (8 * (mm & 3))) & 0xFFu;
+        part[mm] = (mm < p.pq_m) ? s.lut[mm * 256 + code] : 0.0f;
+      }
+#pragma unroll
+      for (int h = 32; h >= 1; h >>= 1)
+#pragma unroll
+        for (int v = 0; v < h; ++v) part[v] = part[v] + part[v + h];
+      s.ckey[lane] = (p.metric == METRIC_IP) ? -part[0] : part[0];
+    }
+  }
+};
+
+// ----------------------------------------------------------------------------
+// Sparse inner product: the query in an LDS hash table, 64 lanes per document
+// (position j of the document feeds partial j mod 64).
+// ----------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t hash_slot(uint32_t t) {
+  return (t * 2654435761u) >> (32 - 9);
+}
+
+struct Sparse {
+  __device__ bool prep(const SearchParams& p, const Lds& s, int64_t q) {
+    const int lane = lane_id();
+    for (int i = lane; i < kHashSlots; i += 64) { s.hkey[i] = kHashEmpty; s.hval[i] = 0.0f; }
+    __syncthreads();
+    const int64_t b = p.q_ptr[q];
+    int64_t e = p.q_ptr[q + 1];
+    const bool ok = e - b <= kHashSlots / 2;
+    if (!ok) e = b + kHashSlots / 2;     // keeps the table at most half full
+    for (int64_t j = b + lane; j < e; j += 64) {
+      const uint32_t t = p.q_ids[j];
+      const float w = p.q_vals[j];
+      uint32_t h = hash_slot(t);
+      while (true) {
+        const uint32_t prev = atomicCAS(&s.hkey[h], kHashEmpty, t);
+        if (prev == kHashEmpty || prev == t) { s.hval[h] = w; break; }
+        h = (h + 1) & (kHashSlots - 1);
+      }
+    }
+    __syncthreads();
+    return ok;
+  }
+
+  __device__ __forceinline__ float weight(const Lds& s, uint32_t t) const {
+    uint32_t h = hash_slot(t);
+    while (true) {
+      const uint32_t k = s.hkey[h];
+      if (k == t) return s.hval[h];
+      if (k == kHashEmpty) return 0.0f;
+      h = (h + 1) & (kHashSlots - 1);
+    }
+  }
+
+  __device__ void score(const SearchParams& p, const Lds& s, int m) {
+    const int lane = lane_id();
+    constexpr int U = 4;
+    for (int base = 0; base < m; base += U) {
+      float acc[U];
+      int64_t b[U], e[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        acc[u] = 0.0f;
+        const int ci = base + u;
+        const int64_t r = (ci < m) ? s.cid[ci] : 0;
+        b[u] = (ci < m) ? p.sp_ptr[r] : 0;
+        e[u] = (ci < m) ? p.sp_ptr[r + 1] : 0;
+      }
+      int64_t most = 0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) most = (e[u] - b[u] > most) ? e[u] - b[u] : most;
+      for (int64_t off = lane; off < most; off += 64) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t j = b[u] + off;
+          if (j < e[u]) acc[u] = __builtin_fmaf(weight(s, p.sp_ids[j]), p.sp_vals[j], acc[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        float val = acc[u];
+#pragma unroll
+        for (int sft = 32; sft >= 1; sft >>= 1) val = val + __shfl_down(val, sft, 64);
+        if (lane == 0 && base + u < m) s.ckey[base + u] = -val;
+      }
+    }
+  }
+};
+
+// ----------------------------------------------------------------------------
+// beam maintenance in LDS
+// ----------------------------------------------------------------------------
+
+// 64-lane bitonic sort of (key, id), ascending.
+__device__ __forceinline__ void sort64(float& k, uint32_t& id) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int size = 2; size <= 64; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const float ok = __shfl_xor(k, stride, 64);
+      const uint32_t oi = (uint32_t)__shfl_xor((int)id, stride, 64);
+      const bool lower = (lane & stride) == 0;
+      const bool asc = (lane & size) == 0;
+      const bool take = (lower == asc) ? kid_lt(ok, oi, k, id) : kid_lt(k, id, ok, oi);
+      if (take) { k = ok; id = oi; }
+    }
+  }
+}
+
+// first unexpanded entry of W at or after `from`, or -1
+__device__ int next_unexpanded(const Lds& s, int from, int w) {
+  for (int j0 = from; j0 < w; j0 += 64) {
+    const int j = j0 + lane_id();
+    const bool un = j < w && !(s.wid[j] & kExpanded);
+    const uint64_t mk = ballot(un);
+    if (mk) return j0 + __builtin_ctzll(mk);
+  }
+  return -1;
+}
+
+// number of W entries strictly below (k, id): binary search over W[0, w)
+__device__ __forceinline__ int rank_in_w(const Lds& s, int w, float k, uint32_t id) {
+  int lo = 0, hi = w;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (kid_lt(s.wkey[mid], s.wid[mid] & kIdMask, k, id)) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Merge the sorted new entries held by lanes 0..mnew-1 into W (size w,
+// capacity ef).  Returns the new size; *first_pos = where the best new entry
+// landed (or a large value if none).
+__device__ int merge_into_w(const Lds& s, int w, int ef, int mnew, float k, uint32_t id,
+                            int* first_pos) {
+  const int lane = lane_id();
+  int r = 0;
+  if (lane < mnew) {
+    r = rank_in_w(s, w, k, id);
+    s.rnk[lane] = r;
+  }
+  __syncthreads();
+  const int r0 = uniform_int(__shfl(r, 0, 64));
+  // shift the tail [r0, w) up by the number of new entries ranked at or below
+  // each position; highest chunk first so no unread entry is overwritten
+  if (w > r0) {
+    const int top = r0 + ((w - 1 - r0) & ~63);
+    for (int j0 = top; j0 >= r0; j0 -= 64) {
+      const int j = j0 + lane;
+      float wk = 0.0f;
+      uint32_t wi = 0u;
+      int dest = ef;
+      if (j < w) {
+        wk = s.wkey[j];
+        wi = s.wid[j];
+        int lo = 0, hi = mnew;        // count of ranks <= j
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (s.rnk[mid] <= j) lo = mid + 1; else hi = mid;
+        }
+        dest = j + lo;
+      }
+      __syncthreads();
+      if (j < w && dest < ef) { s.wkey[dest] = wk; s.wid[dest] = wi; }
+      __syncthreads();
+    }
+  }
+  if (lane < mnew) {
+    const int pos = r + lane;
+    if (pos < ef) { s.wkey[pos] = k; s.wid[pos] = id; }
+  }
+  __syncthreads();
+  *first_pos = (mnew > 0) ? r0 : 0x7FFFFFFF;
+  const int nw = w + mnew;
+  return nw < ef ? nw : ef;
+}
+
+// ----------------------------------------------------------------------------
+// the search kernel
+// ----------------------------------------------------------------------------
+
+struct QueryState {
+  int evals, expansions, visited;
+  int vlog_n;
+  bool vlog_overflow;
+};
+
+__device__ __forceinline__ void log_visited(const SearchParams& p, int slot, int64_t q,
+                                            QueryState& st, bool isnew, int id, uint64_t mask) {
+  const int idx = mbcnt(mask);
+  if (isnew) {
+    const int pos = st.vlog_n + idx;
+    if (pos < p.vlog_cap) p.vlog[(size_t)slot * p.vlog_cap + pos] = id;
+    const int vpos = st.visited + idx;
+    if (p.out_visited && vpos < p.visited_cap) p.out_visited[q * p.visited_cap + vpos] = id;
+  }
+  const int cnt = __builtin_popcountll(mask);
+  if (st.vlog_n + cnt > p.vlog_cap) st.vlog_overflow = true;
+  st.vlog_n += cnt;
+  st.visited += cnt;
+}
+
+template <class Policy>
+__device__ void run_query(const SearchParams& p, const Lds& s, Policy& pol, int slot, int64_t q) {
+  const int lane = lane_id();
+  int k = p.k_arr ? p.k_arr[q] : p.k_all;
+  int ef = p.ef_arr ? p.ef_arr[q] : p.ef_all;
+  int status = 0;
+  if (k > p.k_max) { k = p.k_max; status = 1; }
+  if (k < 1) { k = 1; status = 1; }
+  if (ef < k) ef = k;
+  if (ef > p.ef_cap) { ef = p.ef_cap; status = 1; }
+  k = uniform_int(k);
+  ef = uniform_int(ef);
+
+  // FP32 query copy in LDS for the rerank and the PQ tables
+  if (p.q_lds_floats > 0 && p.queries) {
+    const float* qrow = p.queries + (size_t)q * p.d;
+    for (int i = lane; i < p.q_lds_floats; i += 64) s.q[i] = (i < p.d) ? qrow[i] : 0.0f;
+  }
+  __syncthreads();
+  if (!pol.prep(p, s, q)) status |= 2;
+
+  QueryState st{0, 0, 0, 0, false};
+  uint32_t* bits = p.bits + (size_t)slot * p.bits_words;
+
+  // entry point
+  int cur = p.entry;
+  if (lane == 0) s.cid[0] = cur;
+  __syncthreads();
+  pol.score(p, s, 1);
+  __syncthreads();
+  float ckey = s.ckey[0];
+  st.evals += 1;
+
+  // greedy descent, layers max_level .. 1
+  for (int lc = p.max_level; lc >= 1; --lc) {
+    while (true) {
+      const int off = p.upper_off[cur];
+      int nb = -1;
+      if (lane < p.M && off >= 0) nb = p.upper_adj[((size_t)off + lc - 1) * p.M + lane];
+      const uint64_t mk = ballot(nb >= 0);
+      const int m = __builtin_popcountll(mk);
+      if (m == 0) break;
+      if (nb >= 0) s.cid[mbcnt(mk)] = nb;
+      __syncthreads();
+      pol.score(p, s, m);
+      __syncthreads();
+      st.evals += m;
+      float bk = (lane < m) ? s.ckey[lane] : __builtin_inff();
+      uint32_t bi = (lane < m) ? (uint32_t)s.cid[lane] : kIdMask;
+#pragma unroll
+      for (int sft = 32; sft >= 1; sft >>= 1) {
+        const float ok = __shfl_xor(bk, sft, 64);
+        const uint32_t oi = (uint32_t)__shfl_xor((int)bi, sft, 64);
+        if (kid_lt(ok, oi, bk, bi)) { bk = ok; bi = oi; }
+      }
+      __syncthreads();
+      if (kid_lt(bk, bi, ckey, (uint32_t)cur)) {
+        cur = uniform_int((int)bi);
+        ckey = __builtin_bit_cast(float, uniform_int(__builtin_bit_cast(int, bk)));
+      } else {
+        break;
+      }
+    }
+  }
+
+  // layer 0
+  {
+    const uint32_t bit = 1u << (cur & 31);
+    uint32_t old = 0;
+    if (lane == 0) old = atomicOr(&bits[cur >> 5], bit);
+    const bool isnew = (lane == 0) && !(old & bit);
+    log_visited(p, slot, q, st, isnew, cur, ballot(isnew));
+  }
+  if (lane == 0) { s.wkey[0] = ckey; s.wid[0] = (uint32_t)cur; }
+  __syncthreads();
+  int w = 1;
+  int hint = 0;
+  while (true) {
+    const int cpos = next_unexpanded(s, hint, w);
+    if (cpos < 0) break;
+    const int c = (int)(s.wid[cpos] & kIdMask);
+    __syncthreads();
+    if (lane == 0) s.wid[cpos] = (uint32_t)c | kExpanded;
+    hint = cpos + 1;
+    st.expansions += 1;
+    int nb = (lane < p.M0) ? p.adj0[(size_t)c * p.M0 + lane] : -1;
+    bool isnew = false;
+    if (nb >= 0) {
+      const uint32_t bit = 1u << (nb & 31);
+      const uint32_t old = atomicOr(&bits[nb >> 5], bit);
+      isnew = !(old & bit);
+    }
+    const uint64_t mk = ballot(isnew);
+    const int m = __builtin_popcountll(mk);
+    log_visited(p, slot, q, st, isnew, nb, mk);
+    if (m == 0) { __syncthreads(); continue; }
+    if (isnew) s.cid[mbcnt(mk)] = nb;
+    __syncthreads();
+    pol.score(p, s, m);
+    __syncthreads();
+    st.evals += m;
+    float kk = __builtin_inff();
+    uint32_t ki = kIdMask;
+    bool keep = false;
+    if (lane < m) {
+      kk = s.ckey[lane];
+      ki = (uint32_t)s.cid[lane];
+      keep = (w < ef) || kid_lt(kk, ki, s.wkey[ef - 1], s.wid[ef - 1] & kIdMask);
+    }
+    const int mnew = __builtin_popcountll(ballot(keep));
+    if (mnew == 0) { __syncthreads(); continue; }
+    if (!keep) { kk = __builtin_inff(); ki = kIdMask; }
+    sort64(kk, ki);
+    __syncthreads();
+    int first_pos;
+    w = merge_into_w(s, w, ef, mnew, kk, ki, &first_pos);
+    if (first_pos < hint) hint = first_pos;
+  }
+
+  // rerank with the FP32 rows
+  int nres = w;
+  if (p.rerank > 0) {
+    int R = p.rerank > k ? p.rerank : k;
+    if (R > w) R = w;
+    nres = R;
+    const int nch = p.d / 4;   // FP32 chunks
+    for (int i0 = 0; i0 < R; i0 += 4) {
+      // four rows at a time, 64 lanes per row
+      uint4 raw[4][4];
+      int rid[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        rid[u] = (i0 + u < R) ? (int)(s.wid[i0 + u] & kIdMask) : -1;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int g = lane + 64 * t;
+          raw[u][t] = (rid[u] >= 0 && g < nch)
+              ? *(const uint4*)(p.x_f32 + (size_t)rid[u] * p.d + (size_t)g * 4)
+              : make_uint4(0u, 0u, 0u, 0u);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int g = lane + 64 * t;
+          if (g < nch) {
+            const float* qc = s.q + g * 4;
+            if (p.metric == METRIC_IP) {
+              acc = __builtin_fmaf(qc[0], __uint_as_float(raw[u][t].x), acc);
+              acc = __builtin_fmaf(qc[1], __uint_as_float(raw[u][t].y), acc);
+              acc = __builtin_fmaf(qc[2], __uint_as_float(raw[u][t].z), acc);
+              acc = __builtin_fmaf(qc[3], __uint_as_float(raw[u][t].w), acc);
+            } else {
+              const float t0 = qc[0] - __uint_as_float(raw[u][t].x);
+              const float t1 = qc[1] - __uint_as_float(raw[u][t].y);
+              const float t2 = qc[2] - __uint_as_float(raw[u][t].z);
+              const float t3 = qc[3] - __uint_as_float(raw[u][t].w);
+              acc = __builtin_fmaf(t0, t0, acc);
+              acc = __builtin_fmaf(t1, t1, acc);
+              acc = __builtin_fmaf(t2, t2, acc);
+              acc = __builtin_fmaf(t3, t3, acc);
+            }
+          }
+        }
+#pragma unroll
+        for (int sft = 32; sft >= 1; sft >>= 1) acc = acc + __shfl_down(acc, sft, 64);
+        if (lane == 0 && rid[u] >= 0) s.rk[i0 + u] = (p.metric == METRIC_IP) ? -acc : acc;
+      }
+    }
+    __syncthreads();
+    // rank by (key, id) and write the first k
+    for (int i = lane; i < R; i += 64) {
+      const float ki = s.rk[i];
+      const uint32_t ii = s.wid[i] & kIdMask;
+      int rank = 0;
+      for (int jj = 0; jj < R; ++jj) rank += kid_lt(s.rk[jj], s.wid[jj] & kIdMask, ki, ii) ? 1 : 0;
+      if (rank < k) {
+        p.out_ids[q * p.k_max + rank] = (int64_t)ii;
+        p.out_dists[q * p.k_max + rank] = ki;
+      }
+    }
+  } else {
+    for (int i = lane; i < k && i < w; i += 64) {
+      p.out_ids[q * p.k_max + i] = (int64_t)(s.wid[i] & kIdMask);
+      p.out_dists[q * p.k_max + i] = s.wkey[i];
+    }
+  }
+  for (int i = lane; i < p.k_max; i += 64) {
+    if (i >= k || i >= nres) {
+      p.out_ids[q * p.k_max + i] = -1;
+      p.out_dists[q * p.k_max + i] = __builtin_inff();
+    }
+  }
+  if (lane == 0) {
+    if (p.out_status) p.out_status[q] = status;
+    if (p.out_stats) {
+      p.out_stats[q * 4 + 0] = st.evals;
+      p.out_stats[q * 4 + 1] = st.expansions;
+      p.out_stats[q * 4 + 2] = st.visited;
+      p.out_stats[q * 4 + 3] = w;
+    }
+  }
+  if (p.out_visited) {
+    for (int64_t i = st.visited + lane; i < p.visited_cap; i += 64) p.out_visited[q * p.visited_cap + i] = -1;
+  }
+
+  // leave the slot's visited bits clear for the next query
+  if (!st.vlog_overflow) {
+    const int32_t* lg = p.vlog + (size_t)slot * p.vlog_cap;
+    for (int i = lane; i < st.vlog_n; i += 64) bits[lg[i] >> 5] = 0u;
+  } else {
+    for (int64_t i = lane; i < p.bits_words; i += 64) bits[i] = 0u;
+  }
+  __threadfence();
+  __syncthreads();
+}
+
+template <class Policy>
+__global__ void __launch_bounds__(64) search_kernel(SearchParams p) {
+  extern __shared__ __align__(16) char lds_raw[];
+  const Lds s = carve(lds_raw, p);
+  Policy pol;
+  const int slot = blockIdx.x;
+  while (true) {
+    int qi = 0;
+    if (lane_id() == 0) qi = atomicAdd(p.counter, 1);
+    qi = uniform_int(__shfl(qi, 0, 64));
+    if (qi >= p.nq) break;
+    run_query(p, s, pol, slot, (int64_t)qi);
+  }
+}
+
+__global__ void reset_counter_kernel(int32_t* c) { *c = 0; }
+
+// ----------------------------------------------------------------------------
+// dispatch
+// ----------------------------------------------------------------------------
+
+template <class Policy>
+static hipError_t launch(const SearchParams& p, int slots, size_t lds, hipStream_t st) {
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, p.counter);
+  hipLaunchKernelGGL(search_kernel<Policy>, dim3(slots), dim3(64), lds, st, p);
+  return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t launch_dense(const SearchParams& p, int slots, size_t lds, hipStream_t st) {
+  const int L = p.lanes_per_row, cpl = (p.nchunks + L - 1) / L;
+  if (L == 64) {
+    if (cpl <= 1) return launch<Dense<MODE, 64, 1>>(p, slots, lds, st);
+    if (cpl <= 2) return launch<Dense<MODE, 64, 2>>(p, slots, lds, st);
+    if (cpl <= 3) return launch<Dense<MODE, 64, 3>>(p, slots, lds, st);
+    if (cpl <= 4) return launch<Dense<MODE, 64, 4>>(p, slots, lds, st);
+  } else if (L == 32) {
+    if (cpl <= 1) return launch<Dense<MODE, 32, 1>>(p, slots, lds, st);
+    if (cpl <= 2) return launch<Dense<MODE, 32, 2>>(p, slots, lds, st);
+    if (cpl <= 4 && MODE == MODE_F32) return launch<Dense<MODE, 32, 4>>(p, slots, lds, st);
+  } else if (L == 16) {
+    if (cpl <= 1) return launch<Dense<MODE, 16, 1>>(p, slots, lds, st);
+    if (cpl <= 2) return launch<Dense<MODE, 16, 2>>(p, slots, lds, st);
+    if (cpl <= 4 && MODE == MODE_F32) return launch<Dense<MODE, 16, 4>>(p, slots, lds, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+bool dense_shape_supported(int mode, int nchunks, int L) {
+  if (L != 16 && L != 32 && L != 64) return false;
+  const int cpl = (nchunks + L - 1) / L;
+  if (L == 64) return cpl <= 4;
+  if (mode == MODE_F32) return cpl <= 4;
+  return cpl <= 2;
+}
+
+hipError_t launch_search(const SearchParams& p, int slots, size_t lds, hipStream_t st) {
+  switch (p.mode) {
+    case MODE_F32: return launch_dense<MODE_F32>(p, slots, lds, st);
+    case MODE_F16: return launch_dense<MODE_F16>(p, slots, lds, st);
+    case MODE_BF16: return launch_dense<MODE_BF16>(p, slots, lds, st);
+    case MODE_FP8: return launch_dense<MODE_FP8>(p, slots, lds, st);
+    case MODE_PQ: return launch<PQ>(p, slots, lds, st);
+    case MODE_SPARSE: return launch<Sparse>(p, slots, lds, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+size_t lds_bytes(const SearchParams& p) {
+  auto al = [](size_t b) { return (b + 15) & ~size_t(15); };
+  size_t b = 0;
+  b += al(4 * (size_t)p.ef_cap) * 2;
+  b += al(4 * 64) * 3;
+  b += al(4 * (size_t)p.q_lds_floats);
+  b += al(p.rerank > 0 ? 4 * (size_t)p.ef_cap : 0);
+  b += al(p.mode == MODE_PQ ? 4 * (size_t)p.pq_m * 256 : 0);
+  b += al(p.mode == MODE_SPARSE ? 4 * kHashSlots : 0) * 2;
+  return b;
+}
+
+const void* kernel_symbol(const SearchParams& p) {
+  const int L = p.lanes_per_row, cpl = (p.nchunks + L - 1) / L;
+#define ANN_DENSE_SYM(MODE)                                                             \
+  if (L == 64) {                                                                        \
+    if (cpl <= 1) return (const void*)search_kernel<Dense<MODE, 64, 1>>;                \
+    if (cpl <= 2) return (const void*)search_kernel<Dense<MODE, 64, 2>>;                \
+    if (cpl <= 3) return (const void*)search_kernel<Dense<MODE, 64, 3>>;                \
+    return (const void*)search_kernel<Dense<MODE, 64, 4>>;                              \
+  }                                                                                     \
+  if (L == 32) {                                                                        \
+    if (cpl <= 1) return (const void*)search_kernel<Dense<MODE, 32, 1>>;                \
+    if (cpl <= 2) return (const void*)search_kernel<Dense<MODE, 32, 2>>;                \
+    if (MODE == MODE_F32) return (const void*)search_kernel<Dense<MODE, 32, 4>>;        \
+    return nullptr;                                                                     \
+  }                                                                                     \
+  if (cpl <= 1) return (const void*)search_kernel<Dense<MODE, 16, 1>>;                  \
+  if (cpl <= 2) return (const void*)search_kernel<Dense<MODE, 16, 2>>;                  \
+  if (MODE == MODE_F32) return (const void*)search_kernel<Dense<MODE, 16, 4>>;          \
+  return nullptr;
+  switch (p.mode) {
+    case MODE_F32: { ANN_DENSE_SYM(MODE_F32) }
+    case MODE_F16: { ANN_DENSE_SYM(MODE_F16) }
+    case MODE_BF16: { ANN_DENSE_SYM(MODE_BF16) }
+    case MODE_FP8: { ANN_DENSE_SYM(MODE_FP8) }
+    case MODE_PQ: return (const void*)search_kernel<PQ>;
+    case MODE_SPARSE: return (const void*)search_kernel<Sparse>;
+  }
+#undef ANN_DENSE_SYM
+  return nullptr;
+}
+
+}  // namespace ann

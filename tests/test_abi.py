@@ -1,0 +1,101 @@
+"""The C-ABI library: loads, exports every declared symbol, rejects bad
+arguments on the host (no GPU needed for any of these)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2501_06121_amd as ann
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "ann.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(ann_\w+)\s*\(", text, flags=re.M))
+
+
+def test_library_loads_and_exports_all_declared_symbols():
+    L = ann.lib()
+    decl = declared_functions()
+    assert decl == set(ann.SIGNATURES), decl ^ set(ann.SIGNATURES)
+    for name in decl:
+        assert hasattr(L, name), name
+    assert ann.ann_version() == 1
+
+
+def test_struct_layouts_match_the_c_header(tmp_path):
+    """ctypes mirrors vs. what gcc lays out from include/ann.h."""
+    import subprocess
+    structs = {"ann_index_desc": ann.AnnIndexDesc, "ann_batch": ann.AnnBatch,
+               "ann_launch_cfg": ann.AnnLaunchCfg, "ann_index_info": ann.AnnIndexInfo,
+               "ann_server_cfg": ann.AnnServerCfg, "ann_request": ann.AnnRequest,
+               "ann_completion": ann.AnnCompletion}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ann.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(l.split() for l in subprocess.check_output([str(exe)], text=True).splitlines())
+    for cname, py in structs.items():
+        assert int(got[cname]) == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+
+
+def test_null_arguments_rejected():
+    L = ann.lib()
+    out = C.c_void_p()
+    assert L.ann_index_create(None, 0, C.byref(out)) == ann.ANN_EINVAL
+    assert "NULL" in L.ann_last_error().decode()
+    assert L.ann_search(None, None, 0, 10, 10, None, None) == ann.ANN_EINVAL
+    assert L.ann_search_ex(None, None, None) == ann.ANN_EINVAL
+    assert L.ann_index_free(None) == ann.ANN_OK
+
+
+class _G:
+    def __init__(self, n, M=4, M0=8):
+        self.n, self.M, self.M0, self.max_level, self.entry = n, M, M0, 0, 0
+        self.levels = np.zeros(n, np.uint8)
+        self.adj0 = np.full((n, M0), -1, np.int32)
+        for v in range(n):
+            self.adj0[v, 0] = (v + 1) % n
+        self.upper_off = np.full(n, -1, np.int32)
+        self.upper_adj = np.zeros((0, M), np.int32)
+
+
+def test_malformed_graphs_rejected_before_device_use():
+    X = np.zeros((8, 16), np.float32)
+    g = _G(8)
+    g.adj0[3, 0] = 99                     # id out of range
+    with pytest.raises(ann.AnnError) as e:
+        ann.ann_index_create(g, "l2", 16, x_f32=X)
+    assert e.value.code == ann.ANN_EFORMAT
+    g = _G(8)
+    g.adj0[2, :2] = [-1, 4]               # valid id after padding
+    with pytest.raises(ann.AnnError) as e:
+        ann.ann_index_create(g, "l2", 16, x_f32=X)
+    assert e.value.code == ann.ANN_EFORMAT
+    g = _G(8)
+    g.levels[5] = 1                       # above max_level
+    with pytest.raises(ann.AnnError) as e:
+        ann.ann_index_create(g, "l2", 16, x_f32=X)
+    assert e.value.code == ann.ANN_EFORMAT
+    with pytest.raises(ann.AnnError) as e:  # d not a multiple of 16
+        ann.ann_index_create(_G(8), "l2", 12, x_f32=np.zeros((8, 12), np.float32))
+    assert e.value.code == ann.ANN_EFORMAT
+
+
+@pytest.mark.skipif(ann.ann_device_count() > 0, reason="checks the no-GPU path")
+def test_no_device_reported():
+    with pytest.raises(ann.AnnError) as e:
+        ann.ann_index_create(_G(8), "l2", 16, x_f32=np.zeros((8, 16), np.float32))
+    assert e.value.code == ann.ANN_ENODEV
