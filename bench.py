@@ -1,0 +1,339 @@
+#!/usr/bin/env python3
+"""Benchmark of batched HNSW search on one MI355X.
+
+Workload (default `vmf1m`): 1,000,000 unit-norm FP32 vectors, d = 768, from a
+1,024-cluster von Mises-Fisher mixture (kappa 50), inner product, HNSW with
+M = 32 (M0 = 64) built by the CPU oracle on the FP32 originals; 10,000
+queries from the same mixture; k = 10.  The inputs are synthetic stand-ins
+for the paper's MS MARCO embedding sets (Section 3, Table 1), regenerated
+from their seed; the graph and the exact ground truth come from files the
+oracle wrote (oracle/build_index.py).
+
+One step = one search of all queries in one persistent launch: FP16 rows for
+the traversal, then an exact FP32 re-score of the first 4k beam entries
+(the headline mode), at the smallest ef whose recall@10 reaches 0.95 in the
+committed sweep (profiles/vmf1m_ef_sweep.json), or the largest ef measured.
+The same search with FP32 rows (no rerank) is timed beside it.
+
+Prints ONE JSON line with QPS, ms per step, recall@10, p50/p99 latency under
+Poisson arrivals (continuous-batching server), the roofline of the search
+kernel (algorithmic bytes / kernel time, HIP events on the launch stream)
+and the oracle's CPU throughput on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def load_workload(name, nq=None):
+    import synth
+    spec = synth.WORKLOADS[name]
+    ddir = os.path.join(ROOT, "data", name)
+    gpath = os.path.join(ddir, "graph.npz")
+    if not os.path.exists(gpath):
+        raise SystemExit(f"missing {gpath}: build it with `python -m oracle.build_index {name}`")
+    z = np.load(gpath)
+    n, M, M0, L, e = (int(v) for v in z["meta"])
+
+    class G:
+        pass
+    g = G()
+    g.n, g.M, g.M0, g.max_level, g.entry = n, M, M0, L, e
+    g.levels, g.adj0, g.upper_off, g.upper_adj = z["levels"], z["adj0"], z["upper_off"], z["upper_adj"]
+    t = time.time()
+    X = synth.dense_base(spec)
+    Q = synth.dense_queries(spec)
+    if nq:
+        Q = Q[:nq]
+    log(f"regenerated {X.shape} base + {Q.shape} queries in {time.time() - t:.1f}s")
+    gt = None
+    gtp = os.path.join(ddir, "gt.npz")
+    if os.path.exists(gtp):
+        gt = np.load(gtp)["ids"][:Q.shape[0]]
+    return spec, g, X, Q, gt
+
+
+def recall(ids, gt, k=10):
+    ids = ids[:, :k]
+    gt = gt[:, :k]
+    hits = sum(len(set(a[a >= 0].tolist()) & set(b.tolist())) for a, b in zip(ids, gt))
+    return hits / float(k * ids.shape[0])
+
+
+def row_bytes(mode, d):
+    return d * {"f32": 4, "f16": 2, "bf16": 2, "fp8": 1}[mode] + (4 if mode == "fp8" else 0)
+
+
+def algorithmic_bytes(stats, mode, d, M0, k, rerank):
+    """Bytes a search must read/write: every distance evaluation reads one row,
+    every expansion one neighbour list, the rerank R FP32 rows, plus the
+    query and the output rows."""
+    evals = stats[:, 0].astype(np.int64)
+    exps = stats[:, 1].astype(np.int64)
+    w = stats[:, 3].astype(np.int64)
+    rr = np.minimum(np.maximum(rerank, k), w) if rerank else np.zeros_like(w)
+    per_q = evals * row_bytes(mode, d) + exps * M0 * 4 + rr * d * 4 + d * 4 + k * 12
+    return int(per_q.sum())
+
+
+def sweep_ef(name):
+    p = os.path.join(PROFILES, f"{name}_ef_sweep.json")
+    if os.path.exists(p):
+        return json.load(open(p))
+    return None
+
+
+def pick_ef(sweep, mode_key, target=0.95, default=256):
+    if not sweep or mode_key not in sweep:
+        return default, None
+    pts = sorted(sweep[mode_key], key=lambda r: r["ef"])
+    for r in pts:
+        if r["recall"] >= target:
+            return r["ef"], r["recall"]
+    return pts[-1]["ef"], pts[-1]["recall"]
+
+
+class Timed:
+    """Runs one search configuration: K steps bracketed by events on the stream."""
+
+    def __init__(self, ann, torch, ix, mode, Q, k, ef, rerank, stream):
+        self.ann, self.torch, self.ix = ann, torch, ix
+        self.mode, self.Q, self.k, self.ef, self.rerank, self.stream = mode, Q, k, ef, rerank, stream
+        self.out = None
+
+    def step(self, stats=False):
+        r = self.ann.ann_search_ex(self.ix, self.mode, queries=self.Q, k=self.k, ef=self.ef,
+                                   rerank=self.rerank, stream=self.stream, want_stats=stats,
+                                   out=None if stats else self.out)
+        if not stats and self.out is None:
+            self.out = r
+        return r
+
+    def run(self, steps, warmup):
+        torch = self.torch
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(self.stream)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            self.step()
+        e1.record(self.stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return e0.elapsed_time(e1) / steps, wall
+
+
+def serve_latency(ann, ix, Q, k, ef, mode, rerank, qps_peak, seconds=3.0, seed=0):
+    """Open-loop Poisson arrivals at half the measured peak; p50/p99 ms."""
+    import synth
+    rate = max(100.0, 0.5 * qps_peak)
+    n_req = int(min(Q.shape[0] * 4, max(200, rate * seconds)))
+    t_arr, qidx, _, _ = synth.arrivals(seed, n_req, rate, k_choices=(k,), ef_choices=(ef,),
+                                       n_pool=Q.shape[0])
+    srv = ann.Server(ix, mode=mode, rerank=rerank, max_inflight=8192, max_batch=2048, streams=2,
+                     k_max=max(k, 10), ef_max=ef)
+    lat = []
+    try:
+        t0 = time.perf_counter()
+        i = 0
+        done = 0
+        while done < n_req:
+            now = time.perf_counter() - t0
+            while i < n_req and t_arr[i] <= now:
+                if not srv.submit(i, Q[qidx[i]], k, ef):
+                    break
+                i += 1
+            for c in srv.poll():
+                lat.append((c["t_done"] - c["t_submit"]) * 1e3)
+                done += 1
+            if i < n_req and t_arr[i] > now:
+                time.sleep(min(2e-4, t_arr[i] - now))
+    finally:
+        srv.close()
+    lat = np.array(lat)
+    return float(np.percentile(lat, 50)), float(np.percentile(lat, 99)), rate
+
+
+def cpu_baseline(g, X, Q, mode, ef, k, rerank, budget_s=15.0):
+    """The oracle's search (same mode, ef, rerank) on a sample of queries,
+    all host cores (OpenMP across queries)."""
+    import oracle
+    threads = os.cpu_count() or 1
+    if mode == "f16":
+        st = oracle.dense_store(X.astype(np.float16).view(np.uint16), "ip", "f16")
+    else:
+        st = oracle.dense_store(X, "ip")
+    probe = min(threads, Q.shape[0])
+    t = time.perf_counter()
+    oracle.hnsw_search(g, st, k, ef, Q=Q[:probe], rerank_f32=X if rerank else None, rerank=rerank,
+                       threads=threads)
+    dt = time.perf_counter() - t
+    per = dt / probe
+    m = int(max(probe, min(Q.shape[0], budget_s / max(per, 1e-6))))
+    t = time.perf_counter()
+    oracle.hnsw_search(g, st, k, ef, Q=Q[:m], rerank_f32=X if rerank else None, rerank=rerank,
+                       threads=threads)
+    dt = time.perf_counter() - t
+    return {"value": m / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {m} of {Q.shape[0]} queries, same graph, mode, ef and rerank, "
+                      f"{dt:.1f}s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="vmf1m")
+    ap.add_argument("--nq", type=int, default=None)
+    ap.add_argument("--ef", type=int, default=None, help="ef of the headline mode")
+    ap.add_argument("--ef-f32", type=int, default=None)
+    ap.add_argument("--mode", default="f16")
+    ap.add_argument("--rerank", type=int, default=40)
+    ap.add_argument("--k", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--sweep", default=None, help="comma-separated ef values: write the sweep file")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (every index here "
+              "fits one MI355X: queries would be split across replicas)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2501_06121_amd as ann
+    assert torch.cuda.is_available(), "needs a GPU"
+    spec, g, X, Q, gt = load_workload(a.workload, a.nq)
+    d, k = X.shape[1], a.k
+    t = time.time()
+    x16 = X.astype(np.float16).view(np.uint16)
+    ix = ann.ann_index_create(g, spec["metric"], d, x_f32=X, x_f16=x16)
+    log(f"index on device in {time.time() - t:.1f}s ({ix.info()['device_bytes'] / 2**30:.2f} GiB)")
+    dev = "cuda:0"
+    Qd = torch.from_numpy(Q).to(dev)
+    stream = torch.cuda.Stream()
+
+    if a.sweep:
+        res = {}
+        for key, mode, rr in (("f16+rerank", "f16", a.rerank), ("f32", "f32", 0)):
+            pts = []
+            for ef in (int(v) for v in a.sweep.split(",")):
+                tm = Timed(ann, torch, ix, mode, Qd, k, ef, rr, stream)
+                ms, _ = tm.run(1, 1)
+                r = recall(tm.out["ids"].cpu().numpy(), gt, k)
+                pts.append({"ef": ef, "recall": r, "qps": Q.shape[0] / (ms / 1e3)})
+                log(f"sweep {key} ef={ef} recall@10={r:.4f} qps={pts[-1]['qps']:.0f}")
+            res[key] = pts
+        os.makedirs(PROFILES, exist_ok=True)
+        with open(os.path.join(PROFILES, f"{a.workload}_ef_sweep.json"), "w") as f:
+            json.dump({"workload": a.workload, "k": k, "rerank": a.rerank, **res}, f, indent=1)
+        return
+
+    sweep = sweep_ef(a.workload)
+    ef, _ = pick_ef(sweep, "f16+rerank") if a.ef is None else (a.ef, None)
+    ef32, _ = pick_ef(sweep, "f32") if a.ef_f32 is None else (a.ef_f32, None)
+
+    # headline mode
+    head = Timed(ann, torch, ix, a.mode, Qd, k, ef, a.rerank, stream)
+    ms, wall = head.run(a.steps, a.warmup)
+    ids = head.out["ids"].cpu().numpy()
+    rec = recall(ids, gt, k) if gt is not None else None
+    qps = Q.shape[0] / (ms / 1e3)
+    st = head.step(stats=True)
+    torch.cuda.synchronize()
+    stats = st["stats"].cpu().numpy()
+    nbytes = algorithmic_bytes(stats, a.mode, d, g.M0, k, a.rerank)
+    achieved = nbytes / (ms / 1e3) / 1e9
+    log(f"{a.mode}+rerank{a.rerank} ef={ef}: {ms:.2f} ms/step, {qps:.0f} QPS, recall {rec}, "
+        f"{achieved:.0f} GB/s algorithmic")
+
+    # FP32 beside it
+    f32 = Timed(ann, torch, ix, "f32", Qd, k, ef32, 0, stream)
+    ms32, _ = f32.run(a.steps, a.warmup)
+    rec32 = recall(f32.out["ids"].cpu().numpy(), gt, k) if gt is not None else None
+    st32 = f32.step(stats=True)
+    torch.cuda.synchronize()
+    b32 = algorithmic_bytes(st32["stats"].cpu().numpy(), "f32", d, g.M0, k, 0)
+    log(f"f32 ef={ef32}: {ms32:.2f} ms/step, {Q.shape[0] / (ms32 / 1e3):.0f} QPS, recall {rec32}")
+
+    p50 = p99 = rate = None
+    if not a.no_serve:
+        try:
+            p50, p99, rate = serve_latency(ann, ix, Q, k, ef, a.mode, a.rerank, qps)
+            log(f"serving at {rate:.0f} QPS offered: p50 {p50:.2f} ms p99 {p99:.2f} ms")
+        except ann.AnnError as e:
+            log(f"serving skipped: {e}")
+
+    cpu = None
+    if not a.no_cpu:
+        cpu = cpu_baseline(g, X, Q, a.mode, ef, k, a.rerank)
+        log(f"cpu oracle: {cpu['value']:.1f} QPS on {cpu['cores']} threads")
+
+    traffic = None
+    tp = os.path.join(PROFILES, f"search_{a.workload}_traffic.json")
+    if os.path.exists(tp):
+        t = json.load(open(tp))
+        if t.get("ef") == ef and t.get("mode") == a.mode and t.get("kernel_sha") == kernel_sha():
+            traffic = t.get("bytes_per_launch")
+
+    out = {
+        "metric": "QPS at recall@10>=0.95, 1M x 768 HNSW: FP16 traversal + FP32 rerank vs FP32",
+        "value": round(qps, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded vMF mixture; graph and ground truth from the CPU oracle)",
+        "config": {
+            "workload": f"{a.workload}: {spec['n']:,} x {d} unit-norm vMF mixture "
+                        f"({spec['centres']} clusters, kappa {spec['kappa']}), inner product, "
+                        f"HNSW M={spec['M']} efC={spec['efc']}, {Q.shape[0]:,} queries, k={k}",
+            "storage": f"{a.mode} rows, fp32 arithmetic, fp32 rerank of {a.rerank}",
+            "ef": ef, "recall@10": rec,
+            "p50_ms": p50, "p99_ms": p99, "serve_offered_qps": rate,
+            "f32": {"ef": ef32, "qps": round(Q.shape[0] / (ms32 / 1e3), 1), "recall@10": rec32,
+                    "ms_per_step": round(ms32, 3),
+                    "algorithmic_GBps": round(b32 / (ms32 / 1e3) / 1e9, 1)},
+            "wall_s": round(wall, 3),
+        },
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "bytes_per_launch": nbytes},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ix.close()
+
+
+def kernel_sha():
+    import hashlib
+    p = os.path.join(ROOT, "paper_2501_06121_amd", "csrc", "search_kernels.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    main()

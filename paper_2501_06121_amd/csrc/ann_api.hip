@@ -17,11 +17,12 @@
 #include <vector>
 
 #include "ann.h"
+#include "internal.h"
 #include "search_kernels.h"
 
 using namespace ann;
 
-namespace {
+namespace ann {
 
 thread_local std::string g_err;
 
@@ -41,35 +42,23 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(ANN_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define HIP_OR_RETURN(expr, what)             \
-  do {                                        \
-    hipError_t _e = (expr);                   \
-    if (_e != hipSuccess) return hip_fail(_e, what); \
-  } while (0)
+void Workspace::release() {
+  if (bits) (void)hipFree(bits);
+  if (vlog) (void)hipFree(vlog);
+  if (counter) (void)hipFree(counter);
+  if (done) (void)hipEventDestroy(done);
+  bits = nullptr; vlog = nullptr; counter = nullptr; done = nullptr;
+  slots = 0;
+  bytes = 0;
+}
 
-// One set of per-slot scratch arrays.  A launch owns a workspace until its
-// kernels finish; `done` is recorded after them so that the next user (on any
-// stream) waits for it on the device.
-struct Workspace {
-  int device = -1;
-  int64_t slots = 0;
-  int64_t bits_words = 0;
-  int vlog_cap = 0;
-  uint32_t* bits = nullptr;
-  int32_t* vlog = nullptr;
-  int32_t* counter = nullptr;
-  hipEvent_t done = nullptr;
-  bool used = false;
+int64_t slot_bytes(int64_t n) {
+  return ((n + 31) / 32) * 4 + 4 * std::max<int64_t>(256, std::min<int64_t>(n / 64, 1 << 20));
+}
 
-  void release() {
-    if (bits) hipFree(bits);
-    if (vlog) hipFree(vlog);
-    if (counter) hipFree(counter);
-    if (done) hipEventDestroy(done);
-    bits = nullptr; vlog = nullptr; counter = nullptr; done = nullptr;
-    slots = 0;
-  }
-};
+}  // namespace ann
+
+namespace {
 
 template <class T>
 int upload(T** dst, const T* src, size_t count, int64_t* bytes) {
@@ -80,38 +69,6 @@ int upload(T** dst, const T* src, size_t count, int64_t* bytes) {
   *bytes += (int64_t)(count * sizeof(T));
   return ANN_OK;
 }
-
-}  // namespace
-
-struct ann_index {
-  int device = 0;
-  int cu_count = 0;
-  size_t lds_limit = 65536;
-  hipStream_t stream = nullptr;
-  int64_t n = 0;
-  int d = 0, metric = 0, M = 0, M0 = 0, max_level = 0, entry = 0;
-  int64_t n_upper_lists = 0;
-  int32_t* adj0 = nullptr;
-  int32_t* upper_off = nullptr;
-  int32_t* upper_adj = nullptr;
-  float* x_f32 = nullptr;
-  uint16_t* x_f16 = nullptr;
-  uint16_t* x_bf16 = nullptr;
-  uint8_t* x_fp8 = nullptr;
-  float* fp8_scale = nullptr;
-  float* pq_cb = nullptr;
-  uint8_t* pq_codes = nullptr;
-  int pq_m = 0, pq_stride = 0;
-  int64_t* sp_ptr = nullptr;
-  uint16_t* sp_ids = nullptr;
-  float* sp_vals = nullptr;
-  int64_t device_bytes = 0;
-  ann_launch_cfg cfg[6] = {};
-  std::mutex mu;
-  Workspace ws;                      // used by ann_search / ann_search_ex
-};
-
-namespace {
 
 int mode_supported(const ann_index* ix, int mode) {
   switch (mode) {
@@ -183,6 +140,10 @@ int validate_graph(const ann_index_desc* D) {
   return ANN_OK;
 }
 
+}  // namespace
+
+namespace ann {
+
 int ensure_workspace(ann_index* ix, Workspace& ws, int64_t slots) {
   if (ws.slots >= slots && ws.device == ix->device) return ANN_OK;
   if (ws.done) HIP_OR_RETURN(hipEventSynchronize(ws.done), "hipEventSynchronize");
@@ -197,6 +158,7 @@ int ensure_workspace(ann_index* ix, Workspace& ws, int64_t slots) {
   HIP_OR_RETURN(hipEventCreateWithFlags(&ws.done, hipEventDisableTiming), "hipEventCreate");
   ws.slots = slots;
   ws.used = false;
+  ws.bytes = slots * ws.bits_words * 4 + slots * (int64_t)ws.vlog_cap * 4 + 64;
   return ANN_OK;
 }
 
@@ -294,7 +256,7 @@ int64_t pick_slots(const ann_index* ix, const SearchParams& P, int64_t requested
   if (per_cu <= 0) per_cu = 4;
   int64_t slots = requested > 0 ? requested : (int64_t)ix->cu_count * per_cu;
   // bound the visited bitsets to 4 GiB
-  const int64_t per_slot = ((ix->n + 31) / 32) * 4 + 4 * std::max<int64_t>(256, ix->n / 64);
+  const int64_t per_slot = slot_bytes(ix->n);
   slots = std::min<int64_t>(slots, std::max<int64_t>(1, (int64_t(4) << 30) / per_slot));
   slots = std::min<int64_t>(slots, std::max<int64_t>(1, P.nq));
   return std::max<int64_t>(1, slots);
@@ -325,7 +287,7 @@ int run_batch(ann_index* ix, Workspace& ws, const SearchParams& P0, int64_t slot
   return ANN_OK;
 }
 
-}  // namespace
+}  // namespace ann
 
 extern "C" {
 

@@ -99,3 +99,13 @@ def test_no_device_reported():
     with pytest.raises(ann.AnnError) as e:
         ann.ann_index_create(_G(8), "l2", 16, x_f32=np.zeros((8, 16), np.float32))
     assert e.value.code == ann.ANN_ENODEV
+
+
+def test_server_rejects_bad_arguments_on_the_host():
+    L = ann.lib()
+    out = C.c_void_p()
+    cfg = ann.AnnServerCfg(0, 0, 16, 16, 2, 10, 64, 100, 1 << 30)
+    assert L.ann_server_create(None, C.byref(cfg), C.byref(out)) == ann.ANN_EINVAL
+    assert L.ann_server_submit(None, None) == ann.ANN_EINVAL
+    assert L.ann_server_poll(None, None, 0) == -ann.ANN_EINVAL
+    assert L.ann_server_destroy(None) == ann.ANN_OK
