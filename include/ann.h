@@ -248,14 +248,22 @@ int ann_autotune(ann_index* ix, const ann_batch* b, ann_launch_cfg* best);
 /* ---- exact search on matrix cores ---------------------------------------- */
 
 /*
- * Brute-force k-NN over all FP32 rows with matrix-core (MFMA) tiles of
- * Q x X^T followed by an exact FP32 re-score of the preselected candidates
- * in the fixed order above.  queries device f32[nq][d]; out_ids/out_dists
- * device [nq][k], ascending (key, id).  k <= 128.  Asynchronous on `stream`
- * (NULL: index stream, blocking).
+ * Exact k-NN by a full scan (the k-nearest-neighbour problem of Section 1),
+ * for ground truth.  Matrix-core (MFMA, FP32) tiles of Q x X^T preselect 64
+ * candidates per query and row range; the best k + 16 are then re-scored
+ * with the FP32 rows in the fixed FP32 order above and sorted by (key, id).
+ *   queries        device f32[nq][d]
+ *   out_ids        device i64[nq][k], out_dists device f32[nq][k]
+ *   out_certified  optional device i32[nq]: 1 when the result is provably
+ *                  the exact top-k under the fixed-order keys (the gap to
+ *                  every candidate not re-scored exceeds the worst-case
+ *                  difference between the MFMA and fixed-order sums), else 0
+ * 1 <= k <= 48.  Needs x_f32.  Asynchronous on `stream` (NULL: the index
+ * stream, blocking).  Uses a scratch buffer the index keeps (grown on
+ * demand); calls on one index are serialized by the library.
  */
 int ann_bruteforce(const ann_index* ix, const float* queries, int64_t nq, int32_t k,
-                   int64_t* out_ids, float* out_dists, void* stream);
+                   int64_t* out_ids, float* out_dists, int32_t* out_certified, void* stream);
 
 /* ---- serving: continuous batching ------------------------------------------ */
 

@@ -87,7 +87,7 @@ SIGNATURES = {
     "ann_set_launch": ([P, I32, P], C.c_int),
     "ann_get_launch": ([P, I32, P], C.c_int),
     "ann_autotune": ([P, P, P], C.c_int),
-    "ann_bruteforce": ([P, P, I64, I32, P, P, P], C.c_int),
+    "ann_bruteforce": ([P, P, I64, I32, P, P, P, P], C.c_int),
     "ann_server_create": ([P, P, P], C.c_int),
     "ann_server_submit": ([P, P], C.c_int),
     "ann_server_poll": ([P, P, I32], C.c_int),
@@ -341,13 +341,15 @@ def ann_autotune(index, mode="f32", queries=None, sparse=None, k=10, ef=64, rera
 
 
 def ann_bruteforce(index, queries, k, stream=None):
+    """Exact k-NN on matrix cores; returns (ids, dists, certified) tensors."""
     torch = _torch()
     nq = queries.shape[0]
     ids = torch.empty((nq, k), dtype=torch.int64, device=queries.device)
     dists = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
+    cert = torch.empty((nq,), dtype=torch.int32, device=queries.device)
     _check(lib().ann_bruteforce(index.handle, _dptr(queries), nq, int(k), _dptr(ids), _dptr(dists),
-                                _stream_handle(stream)))
-    return ids, dists
+                                _dptr(cert), _stream_handle(stream)))
+    return ids, dists, cert
 
 
 # --------------------------------------------------------------------------

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -353,6 +354,21 @@ int ann_index_create(const ann_index_desc* D, int device, ann_index** out) {
     HIP_OR_RETURN(hipMalloc((void**)&ix->upper_adj, 64), "hipMalloc");
   }
   if ((rc = upload(&ix->x_f32, D->x_f32, n * d, by))) return rc;
+  if (D->x_f32) {
+    double xmax = 0.0, x2max = 0.0;
+    for (size_t v = 0; v < n; ++v) {
+      double s2 = 0.0;
+      for (size_t i = 0; i < d; ++i) {
+        const double x = D->x_f32[v * d + i];
+        xmax = std::max(xmax, std::fabs(x));
+        s2 += x * x;
+      }
+      x2max = std::max(x2max, s2);
+    }
+    // rounded up so that the bounds stay bounds
+    ix->xmax = (float)(xmax * (1.0 + 1e-6));
+    ix->x2max = (float)(x2max * (1.0 + 1e-6));
+  }
   if ((rc = upload(&ix->x_f16, D->x_f16, n * d, by))) return rc;
   if ((rc = upload(&ix->x_bf16, D->x_bf16, n * d, by))) return rc;
   if ((rc = upload(&ix->x_fp8, D->x_fp8, n * d, by))) return rc;
@@ -384,6 +400,7 @@ int ann_index_free(ann_index* ix) {
   hipSetDevice(ix->device);
   hipDeviceSynchronize();
   ix->ws.release();
+  if (ix->bf_scratch) (void)hipFree(ix->bf_scratch);
   void* ptrs[] = {ix->adj0, ix->upper_off, ix->upper_adj, ix->x_f32, ix->x_f16, ix->x_bf16,
                   ix->x_fp8, ix->fp8_scale, ix->pq_cb, ix->pq_codes, ix->sp_ptr, ix->sp_ids,
                   ix->sp_vals};

@@ -65,6 +65,11 @@ struct ann_index {
   uint16_t* sp_ids = nullptr;
   float* sp_vals = nullptr;
   int64_t device_bytes = 0;
+  float xmax = 0.f;                  // max |x_ij| of the FP32 rows
+  float x2max = 0.f;                 // max squared row norm
+  void* bf_scratch = nullptr;        // brute-force candidates and row norms
+  size_t bf_scratch_bytes = 0;
+  bool bf_norms_ready = false;
   ann_launch_cfg cfg[6] = {};
   std::mutex mu;
   ann::Workspace ws;                 // used by ann_search / ann_search_ex

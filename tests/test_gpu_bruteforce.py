@@ -1,0 +1,63 @@
+"""Brute force on matrix cores against the oracle's exact scan."""
+import numpy as np
+import pytest
+
+import oracle
+
+torch = pytest.importorskip("torch")
+ann = pytest.importorskip("paper_2501_06121_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+def check(X, Q, metric, k, g):
+    ix = ann.ann_index_create(g, metric, X.shape[1], x_f32=X)
+    try:
+        ids, d, cert = ann.ann_bruteforce(ix, torch.from_numpy(Q).to("cuda:0"), k)
+        torch.cuda.synchronize()
+        ids, d, cert = ids.cpu().numpy(), d.cpu().numpy(), cert.cpu().numpy()
+    finally:
+        ix.close()
+    ref_ids, ref_k = oracle.bruteforce(oracle.dense_store(X, metric), X.shape[0], k, Q=Q,
+                                       kmode="canon")
+    assert cert.all()
+    assert np.array_equal(ids, ref_ids)
+    assert np.array_equal(d, ref_k)
+
+
+@pytest.mark.parametrize("k", [1, 10, 48])
+def test_bruteforce_l2(gmm10k, k):
+    print("bruteforce l2 k", k, flush=True)
+    check(gmm10k["X"], gmm10k["Q"], "l2", k, gmm10k["graph"])
+
+
+def test_bruteforce_ip_768(vmf_small):
+    print("bruteforce ip 768", flush=True)
+    check(vmf_small["X"], vmf_small["Q"], "ip", 10, vmf_small["graph"])
+
+
+def test_bruteforce_ragged_and_tiny():
+    # n not a multiple of the 64-row tile, nq not a multiple of 128, n < k
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((1000 + 37, 64)).astype(np.float32)
+    Q = rng.standard_normal((131, 64)).astype(np.float32)
+    g = oracle.hnsw_build(X, "ip", 8, 32, np.zeros(X.shape[0]))
+    check(X, Q, "ip", 10, g)
+    Xs = X[:5]
+    gs = oracle.hnsw_build(Xs, "l2", 4, 8, np.zeros(5))
+    ix = ann.ann_index_create(gs, "l2", 64, x_f32=Xs)
+    try:
+        ids, d, cert = ann.ann_bruteforce(ix, torch.from_numpy(Q[:3]).to("cuda:0"), 8)
+        ids = ids.cpu().numpy()
+        assert np.all(ids[:, 5:] == -1) and np.all(np.sort(ids[:, :5], 1) == np.arange(5))
+    finally:
+        ix.close()
+
+
+def test_bruteforce_rejects_bad_k(gmm10k):
+    ix = ann.ann_index_create(gmm10k["graph"], "l2", 128, x_f32=gmm10k["X"])
+    try:
+        with pytest.raises(ann.AnnError):
+            ann.ann_bruteforce(ix, torch.zeros((2, 128), device="cuda:0"), 49)
+    finally:
+        ix.close()
