@@ -91,6 +91,8 @@ def _declare(L):
     L.or_bruteforce.argtypes = [P, P, P, P, P, I64, I64, I32, I32, P, P, I32]
     L.or_hnsw_build.argtypes = [P, I64, I32, I32, I32, I32, P, I64, C.c_double, I64, I32]
     L.or_hnsw_build.restype = P
+    L.or_hnsw_build_sparse.argtypes = [P, P, P, I64, I32, I32, I32, P, I64, C.c_double, I64, I32]
+    L.or_hnsw_build_sparse.restype = P
     L.or_graph_info.argtypes = [P, P]
     L.or_graph_export.argtypes = [P, P, P, P, P]
     L.or_graph_free.argtypes = [P]
@@ -303,9 +305,28 @@ def hnsw_build(X, metric, M, efc, u_levels, seq_prefix=None, batch_frac=0.0, bat
     assert u.shape == (n,)
     if seq_prefix is None:
         seq_prefix = n
+    g = lib().or_hnsw_build(_ptr(X), n, d, METRICS[metric], M, efc, _ptr(u), int(seq_prefix),
+                            float(batch_frac), int(batch_cap), nthreads(threads))
+    return _export(g, n)
+
+
+def hnsw_build_sparse(indptr, ids, vals, vocab, M, efc, u_levels, seq_prefix=None,
+                      batch_frac=0.0, batch_cap=4096, threads=None):
+    """Build over sparse rows (inner product, EXACT merge-join keys)."""
+    ip = _c(indptr, np.int64); ii = _c(ids, np.uint16); vv = _c(vals, np.float32)
+    n = ip.size - 1
+    u = _c(u_levels, np.float64)
+    assert u.shape == (n,)
+    if seq_prefix is None:
+        seq_prefix = n
+    g = lib().or_hnsw_build_sparse(_ptr(ip), _ptr(ii), _ptr(vv), n, int(vocab), M, efc, _ptr(u),
+                                   int(seq_prefix), float(batch_frac), int(batch_cap),
+                                   nthreads(threads))
+    return _export(g, n)
+
+
+def _export(g, n):
     L = lib()
-    g = L.or_hnsw_build(_ptr(X), n, d, METRICS[metric], M, efc, _ptr(u), int(seq_prefix),
-                        float(batch_frac), int(batch_cap), nthreads(threads))
     info = np.zeros(6, np.int64)
     L.or_graph_info(g, _ptr(info))
     n_, M_, M0, max_level, entry, nlists = (int(v) for v in info)

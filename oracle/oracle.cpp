@@ -439,8 +439,15 @@ struct Builder {
   std::vector<std::vector<std::vector<int32_t>>> adj;   // adj[v][lc]
   int max_level = -1; int32_t entry = -1;
 
-  // key between two base points (CANON FP32, symmetric)
-  float key2(int64_t a, int64_t b) const { return dense_key(st, X + (size_t)a * d, b, KEY_CANON); }
+  // key between two base points: CANON FP32 for dense rows (symmetric); for
+  // sparse rows the EXACT merge-join key (symmetric, and cheaper to build with)
+  float key2(int64_t a, int64_t b) const {
+    if (st.mode == MODE_SPARSE) {
+      const int64_t o = st.sp_ptr[a];
+      return sparse_key(st, st.sp_ids + o, st.sp_vals + o, (int)(st.sp_ptr[a + 1] - o), b, KEY_EXACT);
+    }
+    return dense_key(st, X + (size_t)a * d, b, KEY_CANON);
+  }
 
   // Algorithm 4 without candidate extension and without keeping pruned
   // connections: walk candidates by increasing (key, id) to the base and keep
@@ -473,8 +480,13 @@ struct Builder {
   std::vector<std::vector<int32_t>> choose(int64_t i, Visited& vis) {
     std::vector<std::vector<int32_t>> N((size_t)level[i] + 1);
     if (entry < 0) return N;
-    Evaluator ev(&st, KEY_CANON);
-    ev.bind_dense(X + (size_t)i * d);
+    Evaluator ev(&st, st.mode == MODE_SPARSE ? KEY_EXACT : KEY_CANON);
+    if (st.mode == MODE_SPARSE) {
+      const int64_t o = st.sp_ptr[i];
+      ev.bind_sparse(st.sp_ids + o, st.sp_vals + o, (int)(st.sp_ptr[i + 1] - o));
+    } else {
+      ev.bind_dense(X + (size_t)i * d);
+    }
     std::vector<KI> W{KI{ev.key(entry), entry}};
     const int L = max_level, li = level[i];
     for (int lc = L; lc > li; --lc) W = std::vector<KI>{layer_search(ev, W, 1, lc, vis)[0]};
@@ -705,6 +717,8 @@ struct or_graph {
 // batches of max(1, min(batch_cap, done * batch_frac)) whose neighbour
 // searches all see the graph as it was before the batch.  A batch of one is
 // exactly sequential insertion.
+static void* export_graph(Builder& B);
+
 void* or_hnsw_build(const float* X, int64_t n, int d, int metric, int M, int efc,
                     const double* u, int64_t seq_prefix, double batch_frac,
                     int64_t batch_cap, int threads) {
@@ -712,6 +726,26 @@ void* or_hnsw_build(const float* X, int64_t n, int d, int metric, int M, int efc
   B.X = X; B.n = n; B.d = d; B.metric = metric; B.M = M; B.M0 = 2 * M; B.efc = efc;
   B.st.mode = MODE_F32; B.st.metric = metric; B.st.d = d; B.st.f32 = X;
   B.build(u, seq_prefix, batch_frac, batch_cap, std::max(1, threads));
+  return export_graph(B);
+}
+
+// The same construction over sparse rows (inner product), with EXACT
+// merge-join keys.
+void* or_hnsw_build_sparse(const int64_t* indptr, const uint16_t* ids, const float* vals,
+                           int64_t n, int vocab, int M, int efc, const double* u,
+                           int64_t seq_prefix, double batch_frac, int64_t batch_cap,
+                           int threads) {
+  Builder B;
+  B.X = nullptr; B.n = n; B.d = vocab; B.metric = MET_IP; B.M = M; B.M0 = 2 * M; B.efc = efc;
+  B.st.mode = MODE_SPARSE; B.st.metric = MET_IP; B.st.d = vocab;
+  B.st.sp_ptr = indptr; B.st.sp_ids = ids; B.st.sp_vals = vals;
+  B.build(u, seq_prefix, batch_frac, batch_cap, std::max(1, threads));
+  return export_graph(B);
+}
+
+static void* export_graph(Builder& B) {
+  const int64_t n = B.n;
+  const int M = B.M;
   auto* g = new or_graph;
   g->n = n; g->M = M; g->M0 = 2 * M; g->max_level = B.max_level; g->entry = B.entry;
   g->levels = B.level;

@@ -47,27 +47,8 @@ def sparse_small():
     ip, ids, vals = synth.sparse_zipf(7, n, 30, vocab=vocab, which="base")
     qp, qi, qv = synth.sparse_zipf(7, 48, 10, vocab=vocab, which="queries")
     st = oracle.sparse_store(ip, ids, vals, vocab)
-    # The graph is built on the densified originals (inner product), which
-    # give the same keys as the sparse representation in EXACT arithmetic.
-    Xd = np.zeros((n, vocab), np.float32)
-    for r in range(n):
-        Xd[r, ids[ip[r]:ip[r + 1]]] = vals[ip[r]:ip[r + 1]]
-    u = synth.level_uniforms(7, n)
-    g = sparse_graph(st, n, 16, 64, u)
-    return dict(indptr=ip, ids=ids, vals=vals, q=(qp, qi, qv), vocab=vocab, store=st, graph=g,
-                dense=Xd)
-
-
-def sparse_graph(store, n, M, efc, u):
-    """HNSW over sparse rows: the oracle builds on a dense FP32 matrix, so the
-    sparse fixture densifies (vocabulary x rows is small here)."""
-    ip = store.arrays["sp_ptr"]; ids = store.arrays["sp_ids"]; vals = store.arrays["sp_vals"]
-    vocab = store.d
-    pad = (vocab + 15) // 16 * 16
-    Xd = np.zeros((n, pad), np.float32)
-    for r in range(n):
-        Xd[r, ids[ip[r]:ip[r + 1]]] = vals[ip[r]:ip[r + 1]]
-    return oracle.hnsw_build(Xd, "ip", M, efc, u)
+    g = oracle.hnsw_build_sparse(ip, ids, vals, vocab, 16, 64, synth.level_uniforms(7, n))
+    return dict(indptr=ip, ids=ids, vals=vals, q=(qp, qi, qv), vocab=vocab, store=st, graph=g)
 
 
 def small_int_points(seed, n, d, lo=-4, hi=5):

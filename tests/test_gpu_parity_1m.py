@@ -1,0 +1,104 @@
+"""Parity at full size: 1,000,000 x 768 vMF, inner product, HNSW M=32.
+
+The GPU searches all 10,000 queries in one launch, in the configuration the
+benchmark times; sampled queries are then checked one by one against the
+oracle (same graph, same representation, same ef), bit for bit.  Skipped when
+the oracle-built graph (data/vmf1m) is not present.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+ann = pytest.importorskip("paper_2501_06121_amd")
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+DATA = os.path.join(ROOT, "data", "vmf1m")
+
+
+def say(*a):
+    print("[parity-1m]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def big():
+    gpath = os.path.join(DATA, "graph.npz")
+    if not os.path.exists(gpath):
+        pytest.skip("data/vmf1m/graph.npz not built (python -m oracle.build_index vmf1m)")
+    g = oracle.Graph.load(gpath)
+    spec = synth.WORKLOADS["vmf1m"]
+    say("regenerating 1M x 768")
+    X = synth.dense_base(spec)
+    Q = synth.dense_queries(spec)
+    X16 = X.astype(np.float16).view(np.uint16)   # equals oracle.to_f16 (pinned on the CPU)
+    say("uploading")
+    ix = ann.ann_index_create(g, "ip", X.shape[1], x_f32=X, x_f16=X16)
+    gt = None
+    if os.path.exists(os.path.join(DATA, "gt.npz")):
+        gt = np.load(os.path.join(DATA, "gt.npz"))["ids"]
+    yield dict(g=g, X=X, X16=X16, Q=Q, ix=ix, gt=gt)
+    ix.close()
+
+
+def bench_ef():
+    import json
+    p = os.path.join(ROOT, "profiles", "vmf1m_ef_sweep.json")
+    if not os.path.exists(p):
+        return 256, 256
+    s = json.load(open(p))
+
+    def pick(key):
+        pts = sorted(s[key], key=lambda r: r["ef"])
+        for r in pts:
+            if r["recall"] >= 0.95:
+                return r["ef"]
+        return pts[-1]["ef"]
+    return pick("f16+rerank"), pick("f32")
+
+
+@pytest.mark.parametrize("mode", ["f16", "f32"])
+def test_full_batch_sampled_bitexact(big, mode):
+    ef16, ef32 = bench_ef()
+    ef, rr = (ef16, 40) if mode == "f16" else (ef32, 0)
+    say(mode, "ef", ef, "all 10,000 queries on the GPU")
+    q = torch.from_numpy(big["Q"]).to("cuda:0")
+    r = ann.ann_search_ex(big["ix"], mode, queries=q, k=10, ef=ef, rerank=rr, want_stats=True)
+    torch.cuda.synchronize()
+    ids, dists, stats = (r[k].cpu().numpy() for k in ("ids", "dists", "stats"))
+    assert np.all(r["status"].cpu().numpy() == 0)
+    sample = np.random.default_rng(0).choice(big["Q"].shape[0], 48, replace=False)
+    st = oracle.dense_store(big["X16"], "ip", "f16") if mode == "f16" else oracle.dense_store(big["X"], "ip")
+    say("oracle on", len(sample), "sampled queries")
+    ref = oracle.hnsw_search(big["g"], st, 10, ef, Q=big["Q"][sample],
+                             rerank_f32=big["X"] if rr else None, rerank=rr)
+    assert np.array_equal(ids[sample], ref["ids"])
+    assert np.array_equal(dists[sample], ref["keys"])
+    assert np.array_equal(stats[sample, 1], ref["stats"][:, 2])
+    assert np.array_equal(stats[sample, 2], ref["stats"][:, 3])
+    # distances agree with the FP64 evaluation within 1e-5 relative
+    ex = oracle.keys(oracle.dense_store(big["X"], "ip"), big["Q"][sample], ref["ids"], "exact")
+    if mode == "f32" or rr:
+        assert np.all(np.abs(dists[sample] - ex) <= 1e-5 * np.abs(ex) + 1e-7)
+    if big["gt"] is not None:
+        rec_all = oracle.recall_at_k(ids, big["gt"], 10)
+        rec_s = oracle.recall_at_k(ids[sample], big["gt"][sample], 10)
+        say(mode, "recall@10 all", rec_all, "sample", rec_s)
+        assert abs(oracle.recall_at_k(ref["ids"], big["gt"][sample], 10) - rec_s) <= 0.002
+
+
+def test_maximum_ef(big):
+    say("ef = 4096 on 6 queries")
+    Q = big["Q"][:6]
+    r = ann.ann_search_ex(big["ix"], "f16", queries=torch.from_numpy(Q).to("cuda:0"), k=10,
+                          ef=4096, rerank=40, want_stats=True)
+    torch.cuda.synchronize()
+    ref = oracle.hnsw_search(big["g"], oracle.dense_store(big["X16"], "ip", "f16"), 10, 4096, Q=Q,
+                             rerank_f32=big["X"], rerank=40)
+    assert np.array_equal(r["ids"].cpu().numpy(), ref["ids"])
+    assert np.array_equal(r["stats"].cpu().numpy()[:, 2], ref["stats"][:, 3])

@@ -226,3 +226,21 @@ def test_rerank_reorders_by_fp32_keys(vmf_small):
         order = np.lexsort((w, kk))[:10]
         assert np.array_equal(r["ids"][i], w[order])
         assert np.array_equal(r["keys"][i], kk[order])
+
+
+def test_sparse_build_ef_at_least_n_equals_bruteforce():
+    # n <= 2M + 1: layer 0 is connected, so a non-overflowing beam is exhaustive
+    ip, ids, vals = synth.sparse_zipf(4, 33, 12, vocab=200)
+    qp, qi, qv = synth.sparse_zipf(4, 9, 6, vocab=200, which="queries")
+    g = oracle.hnsw_build_sparse(ip, ids, vals, 200, 16, 40, synth.level_uniforms(4, 33))
+    assert len(reachable(g)) == 33
+    st = oracle.sparse_store(ip, ids, vals, 200)
+    r = oracle.hnsw_search(g, st, 8, 33, sparse_q=(qp, qi, qv), kmode="exact")
+    D = np.zeros((33, 200)); Qd = np.zeros((9, 200))
+    for v in range(33):
+        D[v, ids[ip[v]:ip[v + 1]]] = vals[ip[v]:ip[v + 1]]
+    for v in range(9):
+        Qd[v, qi[qp[v]:qp[v + 1]]] = qv[qp[v]:qp[v + 1]]
+    kk = (-(Qd @ D.T)).astype(np.float32)
+    want = np.array([np.lexsort((np.arange(33), row))[:8] for row in kk])
+    assert np.array_equal(r["ids"], want)
