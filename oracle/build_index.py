@@ -46,6 +46,30 @@ def log(*a):
     print(f"[{time.strftime('%H:%M:%S')}]", *a, flush=True)
 
 
+def build_sparse_graph(workload, n, threads):
+    spec = synth.WORKLOADS[workload]
+    ip, ids, vals = synth.sparse_zipf(0, n, spec["nnz_doc"], vocab=spec["vocab"])
+    u = synth.level_uniforms(0, n)
+    log(f"sparse graph {workload} n={n} nnz={ip[-1]} M={spec['M']} efC={spec['efc']}")
+    t = time.time()
+    seq = n if n <= 20000 else SEQ_PREFIX
+    g = oracle.hnsw_build_sparse(ip, ids, vals, spec["vocab"], spec["M"], spec["efc"], u,
+                                 seq_prefix=seq, batch_frac=BATCH_FRAC, batch_cap=BATCH_CAP,
+                                 threads=threads)
+    log(f"graph built in {time.time() - t:.1f}s max_level={g.max_level} entry={g.entry} "
+        f"mean_deg0={(g.adj0 >= 0).sum(1).mean():.2f}")
+    return g
+
+
+def sparse_gt(workload, n, nq, k=100, threads=None):
+    """Exact top-k of the sparse queries by a full EXACT scan (oracle)."""
+    spec = synth.WORKLOADS[workload]
+    ip, ids, vals = synth.sparse_zipf(0, n, spec["nnz_doc"], vocab=spec["vocab"])
+    qp, qi, qv = synth.sparse_zipf(0, nq, spec["nnz_query"], vocab=spec["vocab"], which="queries")
+    st = oracle.sparse_store(ip, ids, vals, spec["vocab"])
+    return oracle.bruteforce(st, n, k, sparse_q=(qp, qi, qv), kmode="exact", threads=threads)
+
+
 def build_graph(workload, n, threads):
     spec = synth.WORKLOADS[workload]
     X = synth.dense_base(spec, n=n)
@@ -115,6 +139,7 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--threads", type=int, default=os.cpu_count())
     ap.add_argument("--what", default="graph,gt")
+    ap.add_argument("--nq", type=int, default=None)
     a = ap.parse_args(argv)
     spec = synth.WORKLOADS[a.workload]
     n = a.n or spec["n"]
@@ -122,6 +147,17 @@ def main(argv=None):
     os.makedirs(out, exist_ok=True)
     what = set(a.what.split(","))
     X = None
+    if spec["kind"] == "sparse":
+        if "graph" in what:
+            g = build_sparse_graph(a.workload, n, a.threads)
+            g.save(os.path.join(out, "graph.npz"))
+            log("wrote", os.path.join(out, "graph.npz"))
+        if "gt" in what:
+            t = time.time()
+            ids, keys = sparse_gt(a.workload, n, a.nq or spec["nq"], threads=a.threads)
+            np.savez(os.path.join(out, "gt.npz"), ids=ids, keys=keys)
+            log(f"gt in {time.time() - t:.1f}s")
+        return
     if "graph" in what:
         g, X = build_graph(a.workload, n, a.threads)
         g.save(os.path.join(out, "graph.npz"))
@@ -129,7 +165,7 @@ def main(argv=None):
     if "gt" in what:
         if X is None:
             X = synth.dense_base(spec, n=n)
-        Q = synth.dense_queries(spec)
+        Q = synth.dense_queries(spec, nq=a.nq)
         t = time.time()
         ids, keys = exact_topk(X, Q, spec["metric"])
         np.savez(os.path.join(out, "gt.npz"), ids=ids, keys=keys)

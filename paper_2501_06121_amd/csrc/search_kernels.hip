@@ -32,6 +32,11 @@
 
 namespace ann {
 
+// 16-byte chunks each lane keeps in flight while scoring rows (4 VGPRs each).
+#ifndef ANN_ROW_CHUNKS
+#define ANN_ROW_CHUNKS 8
+#endif
+
 constexpr uint32_t kExpanded = 0x80000000u;
 constexpr uint32_t kIdMask = 0x7FFFFFFFu;
 constexpr int kHashSlots = 512;               // sparse query table (<= 256 terms)
@@ -88,7 +93,16 @@ struct Lds {
   float* lut;        // [pq_m * 256] PQ lookup table
   uint32_t* hkey;    // [kHashSlots] sparse query terms
   float* hval;       // [kHashSlots]
+  int64_t* sb;       // [64] sparse row extents of one expansion
+  int64_t* se;       // [64]
 };
+
+// Rerank keys held at once: R_eff <= min(max(R, k_max), ef_cap).
+__host__ __device__ inline int rerank_slots(const SearchParams& p) {
+  if (p.rerank <= 0) return 0;
+  const int r = p.rerank > p.k_max ? p.rerank : p.k_max;
+  return r < p.ef_cap ? r : p.ef_cap;
+}
 
 __device__ Lds carve(char* base, const SearchParams& p) {
   Lds s;
@@ -100,10 +114,12 @@ __device__ Lds carve(char* base, const SearchParams& p) {
   s.ckey = (float*)take(sizeof(float) * 64);
   s.rnk = (int32_t*)take(sizeof(int32_t) * 64);
   s.q = (float*)take(sizeof(float) * p.q_lds_floats);
-  s.rk = (float*)take(sizeof(float) * (p.rerank > 0 ? p.ef_cap : 0));
+  s.rk = (float*)take(sizeof(float) * rerank_slots(p));
   s.lut = (float*)take(sizeof(float) * (p.mode == MODE_PQ ? p.pq_m * 256 : 0));
   s.hkey = (uint32_t*)take(sizeof(uint32_t) * (p.mode == MODE_SPARSE ? kHashSlots : 0));
   s.hval = (float*)take(sizeof(float) * (p.mode == MODE_SPARSE ? kHashSlots : 0));
+  s.sb = (int64_t*)take(sizeof(int64_t) * (p.mode == MODE_SPARSE ? 64 : 0));
+  s.se = (int64_t*)take(sizeof(int64_t) * (p.mode == MODE_SPARSE ? 64 : 0));
   return s;
 }
 
@@ -157,7 +173,7 @@ struct Dense {
   static constexpr int C = ElemsPerChunk<MODE>::value;
   static constexpr int G = 64 / L;          // rows per pass
   static constexpr int V = 64 / L;          // virtual partials per lane
-  static constexpr int U = 8 / CPL;         // passes in flight (<= 32 VGPRs of rows)
+  static constexpr int U = (ANN_ROW_CHUNKS / CPL) > 0 ? ANN_ROW_CHUNKS / CPL : 1;  // passes in flight
   float qreg[CPL][C];
 
   __device__ bool prep(const SearchParams& p, const Lds& s, int64_t q) {
@@ -341,34 +357,46 @@ struct Sparse {
 
   __device__ void score(const SearchParams& p, const Lds& s, int m) {
     const int lane = lane_id();
-    constexpr int U = 4;
+    constexpr int U = 8;   // documents in flight
+    // every candidate's extent in one round trip
+    if (lane < m) {
+      const int64_t r = s.cid[lane];
+      s.sb[lane] = p.sp_ptr[r];
+      s.se[lane] = p.sp_ptr[r + 1];
+    }
+    __syncthreads();
     for (int base = 0; base < m; base += U) {
       float acc[U];
       int64_t b[U], e[U];
+      int64_t most = 0;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         acc[u] = 0.0f;
         const int ci = base + u;
-        const int64_t r = (ci < m) ? s.cid[ci] : 0;
-        b[u] = (ci < m) ? p.sp_ptr[r] : 0;
-        e[u] = (ci < m) ? p.sp_ptr[r + 1] : 0;
+        b[u] = (ci < m) ? s.sb[ci] : 0;
+        e[u] = (ci < m) ? s.se[ci] : 0;
+        most = (e[u] - b[u] > most) ? e[u] - b[u] : most;
       }
-      int64_t most = 0;
-#pragma unroll
-      for (int u = 0; u < U; ++u) most = (e[u] - b[u] > most) ? e[u] - b[u] : most;
       for (int64_t off = lane; off < most; off += 64) {
+        uint32_t tid[U];
+        float val[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int64_t j = b[u] + off;
-          if (j < e[u]) acc[u] = __builtin_fmaf(weight(s, p.sp_ids[j]), p.sp_vals[j], acc[u]);
+          tid[u] = (j < e[u]) ? (uint32_t)p.sp_ids[j] : kHashEmpty;
+          val[u] = (j < e[u]) ? p.sp_vals[j] : 0.0f;
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (tid[u] != kHashEmpty) acc[u] = __builtin_fmaf(weight(s, tid[u]), val[u], acc[u]);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
+        if (base + u >= m) break;
         float val = acc[u];
 #pragma unroll
         for (int sft = 32; sft >= 1; sft >>= 1) val = val + __shfl_down(val, sft, 64);
-        if (lane == 0 && base + u < m) s.ckey[base + u] = -val;
+        if (lane == 0) s.ckey[base + u] = -val;
       }
     }
   }
@@ -378,12 +406,11 @@ struct Sparse {
 // beam maintenance in LDS
 // ----------------------------------------------------------------------------
 
-// 64-lane bitonic sort of (key, id), ascending.
-__device__ __forceinline__ void sort64(float& k, uint32_t& id) {
+// Bitonic sort of (key, id), ascending, over lanes [0, n) (n a power of two
+// <= 64, uniform); lanes >= n are untouched.
+__device__ __forceinline__ void sort_lanes(float& k, uint32_t& id, int n) {
   const int lane = lane_id();
-#pragma unroll
-  for (int size = 2; size <= 64; size <<= 1) {
-#pragma unroll
+  for (int size = 2; size <= n; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       const float ok = __shfl_xor(k, stride, 64);
       const uint32_t oi = (uint32_t)__shfl_xor((int)id, stride, 64);
@@ -442,12 +469,18 @@ __device__ int merge_into_w(const Lds& s, int w, int ef, int mnew, float k, uint
       if (j < w) {
         wk = s.wkey[j];
         wi = s.wid[j];
-        int lo = 0, hi = mnew;        // count of ranks <= j
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (s.rnk[mid] <= j) lo = mid + 1; else hi = mid;
+        int cnt = 0;                  // new entries ranked at or below j
+        if (mnew <= 16) {
+          for (int i = 0; i < mnew; ++i) cnt += (__builtin_amdgcn_readlane(r, i) <= j) ? 1 : 0;
+        } else {
+          int lo = 0, hi = mnew;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (s.rnk[mid] <= j) lo = mid + 1; else hi = mid;
+          }
+          cnt = lo;
         }
-        dest = j + lo;
+        dest = j + cnt;
       }
       __syncthreads();
       if (j < w && dest < ef) { s.wkey[dest] = wk; s.wid[dest] = wi; }
@@ -598,10 +631,24 @@ __device__ void run_query(const SearchParams& p, const Lds& s, Policy& pol, int 
       ki = (uint32_t)s.cid[lane];
       keep = (w < ef) || kid_lt(kk, ki, s.wkey[ef - 1], s.wid[ef - 1] & kIdMask);
     }
-    const int mnew = __builtin_popcountll(ballot(keep));
+    const uint64_t km = ballot(keep);
+    const int mnew = __builtin_popcountll(km);
     if (mnew == 0) { __syncthreads(); continue; }
-    if (!keep) { kk = __builtin_inff(); ki = kIdMask; }
-    sort64(kk, ki);
+    // compact the kept entries to lanes [0, mnew), then sort the smallest
+    // power-of-two prefix that holds them
+    if (km != (~0ull >> (64 - mnew))) {
+      __syncthreads();
+      if (keep) { s.ckey[mbcnt(km)] = kk; s.cid[mbcnt(km)] = (int32_t)ki; }
+      __syncthreads();
+      kk = (lane < mnew) ? s.ckey[lane] : __builtin_inff();
+      ki = (lane < mnew) ? (uint32_t)s.cid[lane] : kIdMask;
+    }
+    if (mnew > 1) {
+      int sz = 2;
+      while (sz < mnew) sz <<= 1;
+      if (lane >= mnew) { kk = __builtin_inff(); ki = kIdMask; }
+      sort_lanes(kk, ki, sz);
+    }
     __syncthreads();
     int first_pos;
     w = merge_into_w(s, w, ef, mnew, kk, ki, &first_pos);
@@ -747,6 +794,7 @@ static hipError_t launch_dense(const SearchParams& p, int slots, size_t lds, hip
   } else if (L == 32) {
     if (cpl <= 1) return launch<Dense<MODE, 32, 1>>(p, slots, lds, st);
     if (cpl <= 2) return launch<Dense<MODE, 32, 2>>(p, slots, lds, st);
+    if (cpl <= 3 && MODE != MODE_FP8) return launch<Dense<MODE, 32, 3>>(p, slots, lds, st);
     if (cpl <= 4 && MODE == MODE_F32) return launch<Dense<MODE, 32, 4>>(p, slots, lds, st);
   } else if (L == 16) {
     if (cpl <= 1) return launch<Dense<MODE, 16, 1>>(p, slots, lds, st);
@@ -761,6 +809,7 @@ bool dense_shape_supported(int mode, int nchunks, int L) {
   const int cpl = (nchunks + L - 1) / L;
   if (L == 64) return cpl <= 4;
   if (mode == MODE_F32) return cpl <= 4;
+  if (L == 32 && mode != MODE_FP8) return cpl <= 3;
   return cpl <= 2;
 }
 
@@ -782,9 +831,10 @@ size_t lds_bytes(const SearchParams& p) {
   b += al(4 * (size_t)p.ef_cap) * 2;
   b += al(4 * 64) * 3;
   b += al(4 * (size_t)p.q_lds_floats);
-  b += al(p.rerank > 0 ? 4 * (size_t)p.ef_cap : 0);
+  b += al(4 * (size_t)rerank_slots(p));
   b += al(p.mode == MODE_PQ ? 4 * (size_t)p.pq_m * 256 : 0);
   b += al(p.mode == MODE_SPARSE ? 4 * kHashSlots : 0) * 2;
+  b += al(p.mode == MODE_SPARSE ? 8 * 64 : 0) * 2;
   return b;
 }
 
@@ -800,6 +850,7 @@ const void* kernel_symbol(const SearchParams& p) {
   if (L == 32) {                                                                        \
     if (cpl <= 1) return (const void*)search_kernel<Dense<MODE, 32, 1>>;                \
     if (cpl <= 2) return (const void*)search_kernel<Dense<MODE, 32, 2>>;                \
+    if (cpl <= 3 && MODE != MODE_FP8) return (const void*)search_kernel<Dense<MODE, 32, 3>>; \
     if (MODE == MODE_F32) return (const void*)search_kernel<Dense<MODE, 32, 4>>;        \
     return nullptr;                                                                     \
   }                                                                                     \

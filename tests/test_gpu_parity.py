@@ -115,8 +115,9 @@ def test_768d_ip_bitexact(v768, mode, lanes):
     rr = 0 if mode == "f32" else 40
     ref = oracle.hnsw_search(v768["g"], st, 10, 100, Q=v768["Q"],
                              rerank_f32=v768["X"] if rr else None, rerank=rr, visited_cap=4096)
-    # 768-d rows: 192 FP32 / 96 16-bit chunks need 64 lanes; 48 FP8 chunks fit 32
-    shape_ok = lanes == 64 or mode == "fp8"
+    # 768-d rows: 192 FP32 chunks need 64 lanes; 96 16-bit chunks fit 32 lanes
+    # (3 per lane), 48 FP8 chunks fit 32 lanes (2 per lane)
+    shape_ok = lanes == 64 or mode != "f32"
     if not shape_ok:
         with pytest.raises(ann.AnnError):
             ann.ann_set_launch(v768["ix"], mode, lanes_per_row=lanes)
