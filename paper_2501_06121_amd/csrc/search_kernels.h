@@ -28,8 +28,10 @@ struct SearchParams {
   const int32_t* adj0;
   const int32_t* upper_off;
   const int32_t* upper_adj;
-  // batch
+  // batch (nq_dev, when set, holds the query count on the device and
+  // overrides nq, so that a captured launch can serve batches of any size)
   int64_t nq;
+  const int32_t* nq_dev;
   const float* queries;
   const int64_t* q_ptr;
   const uint16_t* q_ids;

@@ -761,11 +761,12 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams p) {
   const Lds s = carve(lds_raw, p);
   Policy pol;
   const int slot = blockIdx.x;
+  const int64_t nq = p.nq_dev ? (int64_t)uniform_int(*p.nq_dev) : p.nq;
   while (true) {
     int qi = 0;
     if (lane_id() == 0) qi = atomicAdd(p.counter, 1);
     qi = uniform_int(__shfl(qi, 0, 64));
-    if (qi >= p.nq) break;
+    if (qi >= nq) break;
     run_query(p, s, pol, slot, (int64_t)qi);
   }
 }

@@ -9,6 +9,10 @@
 // max_inflight (queries on the device), max_batch (queries per launch) and
 // the device memory budget fixed at creation.
 //
+// Each lane replays one captured HIP graph (queue-counter reset + persistent
+// search kernel) per batch; the kernel reads the batch size from device
+// memory, so the same graph serves batches of every size.
+//
 // Results do not depend on how requests were batched: the kernel evaluates
 // every query with the same fixed arithmetic whatever its neighbours in the
 // batch.
@@ -60,6 +64,10 @@ struct Lane {
   int64_t* dids = nullptr;
   float* dd = nullptr;
   int32_t* dstat = nullptr;
+  int32_t* dnq = nullptr;            // query count of the batch on the device
+  int32_t* hnq = nullptr;
+  hipGraph_t graph = nullptr;        // [counter reset, search] captured once
+  hipGraphExec_t exec = nullptr;
   float* hq = nullptr;
   int32_t* hk = nullptr;
   int32_t* hef = nullptr;
@@ -78,6 +86,7 @@ struct ann_server {
   ann_server_cfg cfg{};
   int64_t slots = 0;
   std::vector<Lane> lanes;
+  SearchParams proto{};              // kernel parameters shared by the lanes
   std::mutex mu;
   std::condition_variable cv;
   std::deque<Req> queue;
@@ -88,6 +97,7 @@ struct ann_server {
   std::thread th;
 
   int launch(Lane& L, std::vector<Req>&& reqs);
+  int capture(Lane& L);
   void collect(Lane& L);
   void loop();
   void free_lanes();
@@ -104,24 +114,9 @@ int ann_server::launch(Lane& L, std::vector<Req>&& reqs) {
   HIP_OR_RETURN(hipMemcpyAsync(L.dq, L.hq, sizeof(float) * (size_t)m * d, hipMemcpyHostToDevice, L.st), "H2D queries");
   HIP_OR_RETURN(hipMemcpyAsync(L.dk, L.hk, sizeof(int32_t) * m, hipMemcpyHostToDevice, L.st), "H2D k");
   HIP_OR_RETURN(hipMemcpyAsync(L.def, L.hef, sizeof(int32_t) * m, hipMemcpyHostToDevice, L.st), "H2D ef");
-  ann_batch b;
-  std::memset(&b, 0, sizeof b);
-  b.mode = cfg.mode;
-  b.rerank = cfg.rerank;
-  b.nq = m;
-  b.queries = L.dq;
-  b.k = L.dk;
-  b.ef = L.def;
-  b.k_max = cfg.k_max;
-  b.ef_max = cfg.ef_max;
-  b.out_ids = L.dids;
-  b.out_dists = L.dd;
-  b.out_status = L.dstat;
-  SearchParams P;
-  int rc = make_params(ix, &b, &P);
-  if (rc) return rc;
-  rc = run_batch(ix, L.ws, P, slots, L.st);
-  if (rc) return rc;
+  *L.hnq = m;
+  HIP_OR_RETURN(hipMemcpyAsync(L.dnq, L.hnq, sizeof(int32_t), hipMemcpyHostToDevice, L.st), "H2D nq");
+  HIP_OR_RETURN(hipGraphLaunch(L.exec, L.st), "hipGraphLaunch");
   const size_t kk = (size_t)m * cfg.k_max;
   HIP_OR_RETURN(hipMemcpyAsync(L.hids, L.dids, sizeof(int64_t) * kk, hipMemcpyDeviceToHost, L.st), "D2H ids");
   HIP_OR_RETURN(hipMemcpyAsync(L.hd, L.dd, sizeof(float) * kk, hipMemcpyDeviceToHost, L.st), "D2H dists");
@@ -130,6 +125,40 @@ int ann_server::launch(Lane& L, std::vector<Req>&& reqs) {
   L.batch = std::move(reqs);
   L.busy = true;
   L.t_start = now_s();
+  return ANN_OK;
+}
+
+// Records the lane's two kernels (queue-counter reset and the persistent
+// search) as a graph: the batch size is read from L.dnq on the device, so one
+// graph serves every batch of the lane.
+int ann_server::capture(Lane& L) {
+  SearchParams P = proto;
+  P.nq = cfg.max_batch;
+  P.nq_dev = L.dnq;
+  P.queries = L.dq;
+  P.k_arr = L.dk;
+  P.ef_arr = L.def;
+  P.out_ids = L.dids;
+  P.out_dists = L.dd;
+  P.out_status = L.dstat;
+  P.bits = L.ws.bits;
+  P.bits_words = L.ws.bits_words;
+  P.vlog = L.ws.vlog;
+  P.vlog_cap = L.ws.vlog_cap;
+  P.counter = L.ws.counter;
+  const size_t lds = lds_bytes(P);
+  if (lds > 65536) {
+    const void* fn = kernel_symbol(P);
+    if (fn) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  }
+  HIP_OR_RETURN(hipStreamBeginCapture(L.st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  const hipError_t le = launch_search(P, (int)std::min<int64_t>(slots, cfg.max_batch), lds, L.st);
+  hipGraph_t g = nullptr;
+  const hipError_t ce = hipStreamEndCapture(L.st, &g);
+  if (le != hipSuccess) { if (g) (void)hipGraphDestroy(g); return hip_fail(le, "captured search launch"); }
+  HIP_OR_RETURN(ce, "hipStreamEndCapture");
+  L.graph = g;
+  HIP_OR_RETURN(hipGraphInstantiate(&L.exec, g, nullptr, nullptr, 0), "hipGraphInstantiate");
   return ANN_OK;
 }
 
@@ -208,10 +237,12 @@ void ann_server::free_lanes() {
   for (Lane& L : lanes) {
     if (L.st) (void)hipStreamSynchronize(L.st);
     L.ws.release();
-    void* dev[] = {L.dq, L.dk, L.def, L.dids, L.dd, L.dstat};
+    if (L.exec) (void)hipGraphExecDestroy(L.exec);
+    if (L.graph) (void)hipGraphDestroy(L.graph);
+    void* dev[] = {L.dq, L.dk, L.def, L.dids, L.dd, L.dstat, L.dnq};
     for (void* p : dev)
       if (p) (void)hipFree(p);
-    void* host[] = {L.hq, L.hk, L.hef, L.hids, L.hd, L.hstat};
+    void* host[] = {L.hq, L.hk, L.hef, L.hids, L.hd, L.hstat, L.hnq};
     for (void* p : host)
       if (p) (void)hipHostFree(p);
     if (L.ev) (void)hipEventDestroy(L.ev);
@@ -232,7 +263,8 @@ int ann_server_create(const ann_index* cix, const ann_server_cfg* cfg, ann_serve
     return fail(ANN_EINVAL, "bad server configuration");
   if (std::max(c.ef_max, c.k_max) > ANN_EF_MAX) return fail(ANN_EBUDGET, "ef_max above ANN_EF_MAX");
   ann_index* ix = const_cast<ann_index*>(cix);
-  // a dry batch validates mode, rerank and the on-chip memory for ef_max
+  // a dry batch validates mode, rerank and the on-chip memory for ef_max,
+  // and gives the kernel parameters every lane shares
   ann_batch b;
   std::memset(&b, 0, sizeof b);
   b.mode = c.mode; b.rerank = c.rerank; b.nq = 0; b.k_all = 1; b.ef_all = 1;
@@ -240,6 +272,7 @@ int ann_server_create(const ann_index* cix, const ann_server_cfg* cfg, ann_serve
   SearchParams P;
   int rc = make_params(ix, &b, &P);
   if (rc) return rc;
+  const SearchParams proto = P;
   std::unique_ptr<ann_server> s(new ann_server);
   s->ix = ix;
   s->cfg = c;
@@ -252,6 +285,7 @@ int ann_server_create(const ann_index* cix, const ann_server_cfg* cfg, ann_serve
   if (c.streams * (batch_bytes + slots * slot_bytes(ix->n)) > c.hbm_budget)
     return fail(ANN_EBUDGET, "hbm_budget %lld too small for one slot per stream", (long long)c.hbm_budget);
   s->slots = slots;
+  s->proto = proto;
   HIP_OR_RETURN(hipSetDevice(ix->device), "hipSetDevice");
   s->lanes.resize(c.streams);
   for (Lane& L : s->lanes) {
@@ -271,8 +305,12 @@ int ann_server_create(const ann_index* cix, const ann_server_cfg* cfg, ann_serve
     HIP_OR_RETURN(hipHostMalloc((void**)&L.hids, sizeof(int64_t) * nb * c.k_max, hipHostMallocDefault), "hipHostMalloc");
     HIP_OR_RETURN(hipHostMalloc((void**)&L.hd, sizeof(float) * nb * c.k_max, hipHostMallocDefault), "hipHostMalloc");
     HIP_OR_RETURN(hipHostMalloc((void**)&L.hstat, sizeof(int32_t) * nb, hipHostMallocDefault), "hipHostMalloc");
+    HIP_OR_RETURN(hipMalloc((void**)&L.dnq, sizeof(int32_t)), "hipMalloc");
+    HIP_OR_RETURN(hipHostMalloc((void**)&L.hnq, sizeof(int32_t), hipHostMallocDefault), "hipHostMalloc");
   }
   s->cfg.max_batch = (int32_t)max_batch;
+  for (Lane& L : s->lanes)
+    if ((rc = s->capture(L))) { s->free_lanes(); return rc; }
   ann_server* raw = s.get();
   s->th = std::thread([raw] { raw->loop(); });
   *out = s.release();
