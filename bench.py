@@ -34,6 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK = 157.3
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -213,6 +214,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--sweep", default=None, help="comma-separated ef values: write the sweep file")
+    ap.add_argument("--sweep-out", default=None, help="where the sweep JSON goes "
+                    "(default profiles/<workload>_ef_sweep.json)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (every index here "
@@ -243,8 +246,9 @@ def main():
                 pts.append({"ef": ef, "recall": r, "qps": Q.shape[0] / (ms / 1e3)})
                 log(f"sweep {key} ef={ef} recall@10={r:.4f} qps={pts[-1]['qps']:.0f}")
             res[key] = pts
-        os.makedirs(PROFILES, exist_ok=True)
-        with open(os.path.join(PROFILES, f"{a.workload}_ef_sweep.json"), "w") as f:
+        path = a.sweep_out or os.path.join(PROFILES, f"{a.workload}_ef_sweep.json")
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        with open(path, "w") as f:
             json.dump({"workload": a.workload, "k": k, "rerank": a.rerank, **res}, f, indent=1)
         return
 
@@ -274,6 +278,28 @@ def main():
     torch.cuda.synchronize()
     b32 = algorithmic_bytes(st32["stats"].cpu().numpy(), "f32", d, g.M0, k, 0)
     log(f"f32 ef={ef32}: {ms32:.2f} ms/step, {Q.shape[0] / (ms32 / 1e3):.0f} QPS, recall {rec32}")
+
+    # exact k-NN on matrix cores (ground truth path): one launch, all queries
+    bf = None
+    try:
+        ann.ann_bruteforce(ix, Qd[:256], k)          # warm the row norms and scratch
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        bids, _, cert = ann.ann_bruteforce(ix, Qd, k, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        bms = e0.elapsed_time(e1)
+        flops = 2.0 * Q.shape[0] * X.shape[0] * d
+        bf = {"ms": round(bms, 2), "tflops": round(flops / (bms / 1e3) / 1e12, 1),
+              "peak_tflops": FP32_MFMA_PEAK, "frac": round(flops / (bms / 1e3) / 1e12 / FP32_MFMA_PEAK, 4),
+              "certified": float(cert.float().mean().item()),
+              "recall@10_vs_oracle_gt": recall(bids.cpu().numpy(), gt, k) if gt is not None else None}
+        log(f"bruteforce: {bms:.1f} ms, {bf['tflops']} TFLOP/s, certified {bf['certified']:.4f}, "
+            f"agreement with oracle GT {bf['recall@10_vs_oracle_gt']}")
+    except ann.AnnError as e:
+        log(f"bruteforce skipped: {e}")
 
     p50 = p99 = rate = None
     if not a.no_serve:
@@ -319,6 +345,7 @@ def main():
                     "ms_per_step": round(ms32, 3),
                     "algorithmic_GBps": round(b32 / (ms32 / 1e3) / 1e9, 1)},
             "wall_s": round(wall, 3),
+            "bruteforce_mfma": bf,
         },
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

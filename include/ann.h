@@ -74,8 +74,11 @@ enum ann_mode {
 };
 
 /* Largest ef (after ef_eff = max(ef, k)) one search can use: the beam lives
- * in on-chip memory.  Larger requests fail with ANN_EBUDGET. */
-#define ANN_EF_MAX 4096
+ * in on-chip memory (8 bytes per entry; 16384 entries take 128 KB of the
+ * 160 KB LDS of a compute unit, leaving one query per unit).  Larger requests
+ * fail with ANN_EBUDGET, as do requests whose on-chip footprint (beam, rerank
+ * keys, PQ table) exceeds the LDS. */
+#define ANN_EF_MAX 16384
 /* Largest k and largest rerank depth. */
 #define ANN_K_MAX 1024
 

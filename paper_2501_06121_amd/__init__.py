@@ -25,7 +25,7 @@ ERR_NAMES = {0: "ANN_OK", 1: "ANN_EINVAL", 2: "ANN_ENODEV", 3: "ANN_ENOMEM", 4: 
              5: "ANN_EFORMAT", 6: "ANN_EHIP", 7: "ANN_EUNSUP", 8: "ANN_EAGAIN"}
 METRIC = {"l2": 0, "ip": 1}
 MODE = {"f32": 0, "f16": 1, "bf16": 2, "fp8": 3, "pq": 4, "sparse": 5}
-ANN_EF_MAX = 4096
+ANN_EF_MAX = 16384
 ANN_K_MAX = 1024
 
 P = C.c_void_p

@@ -78,6 +78,23 @@ __device__ __forceinline__ float e4m3_bits_to_f32(uint32_t b) {
   return __uint_as_float(__float_as_uint(mag) | ((b & 0x80u) << 24));
 }
 
+// Cross-lane levels s = L/2 .. 1 of the fixed fold inside groups of L lanes:
+// afterwards lane 0 of each group holds the group's sum.  At level s lane j
+// (j < s) adds the value of lane j + s: DPP row shifts for s <= 8 (rows of 16
+// lanes), a swizzle (xor 16 inside 32 lanes) for s = 16, a permute for s = 32.
+template <int L>
+__device__ __forceinline__ float fold_lanes(float v) {
+  if constexpr (L >= 64) v = v + __shfl_down(v, 32, 64);
+  if constexpr (L >= 32)
+    v = v + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), (0x10 << 10) | 0x1F));
+  if constexpr (L >= 16)
+    v = v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x108, 0xF, 0xF, true));
+  v = v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x104, 0xF, 0xF, true));
+  v = v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x102, 0xF, 0xF, true));
+  v = v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x101, 0xF, 0xF, true));
+  return v;
+}
+
 // ----------------------------------------------------------------------------
 // shared-memory layout of one wave (dynamic LDS)
 // ----------------------------------------------------------------------------
@@ -233,10 +250,8 @@ struct Dense {
         for (int h = V / 2; h >= 1; h >>= 1)
 #pragma unroll
           for (int v = 0; v < h; ++v) acc[v] = acc[v] + acc[v + h];
-        float val = acc[0];
         // levels s = L/2 .. 1 across the lanes of the group
-#pragma unroll
-        for (int sft = L / 2; sft >= 1; sft >>= 1) val = val + __shfl_down(val, sft, L);
+        float val = fold_lanes<L>(acc[0]);
         const int ci = base + u * G + grp;
         if (j == 0 && ci < m) {
           float key;
@@ -393,9 +408,7 @@ struct Sparse {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (base + u >= m) break;
-        float val = acc[u];
-#pragma unroll
-        for (int sft = 32; sft >= 1; sft >>= 1) val = val + __shfl_down(val, sft, 64);
+        const float val = fold_lanes<64>(acc[u]);
         if (lane == 0) s.ckey[base + u] = -val;
       }
     }
@@ -702,8 +715,7 @@ __device__ void run_query(const SearchParams& p, const Lds& s, Policy& pol, int 
             }
           }
         }
-#pragma unroll
-        for (int sft = 32; sft >= 1; sft >>= 1) acc = acc + __shfl_down(acc, sft, 64);
+        acc = fold_lanes<64>(acc);
         if (lane == 0 && rid[u] >= 0) s.rk[i0 + u] = (p.metric == METRIC_IP) ? -acc : acc;
       }
     }

@@ -195,7 +195,7 @@ def test_edge_cases(c1):
     assert np.array_equal(a["ids"], b["ids"])
     # over-capacity requests fail on the host
     with pytest.raises(ann.AnnError) as e:
-        gpu(ix, "f32", c1["Q"][:2], 10, 5000)
+        gpu(ix, "f32", c1["Q"][:2], 10, 20000)
     assert e.value.code == ann.ANN_EBUDGET
     # a 3-node graph: fewer nodes than k -> padding
     X = np.zeros((3, 16), np.float32); X[:, 0] = [0, 1, 5]
