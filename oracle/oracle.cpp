@@ -40,6 +40,7 @@
 #include <cstdint>
 #include <cstring>
 #include <cstdlib>
+#include <cstdio>
 #include <vector>
 #include <queue>
 #include <algorithm>
@@ -558,6 +559,9 @@ struct Builder {
         const int64_t i = done + t;
         if ((int)level[i] > max_level) { max_level = level[i]; entry = (int32_t)i; }
       }
+      const int64_t step = std::max<int64_t>(1, n / 20);
+      if (n >= 100000 && (done + b) / step != done / step)
+        std::fprintf(stderr, "[oracle build] %lld / %lld nodes\n", (long long)(done + b), (long long)n);
       done += b;
     }
   }

@@ -132,24 +132,52 @@ def vmf_mixture(seed, n, d, n_centres, kappa, which="base", threads=None):
 # Sparse: Zipf term ids, log-normal weights (SPLADE-like shape, IP)
 # --------------------------------------------------------------------------
 
+def _first_distinct(D, nnz, vocab):
+    """Per row of D (-1 = invalid draw): the first nnz[r] distinct valid values
+    in draw order, returned id-sorted and padded with `vocab`; and whether the
+    row had enough."""
+    m, w = D.shape
+    order = np.argsort(D, axis=1, kind="stable")
+    S = np.take_along_axis(D, order, axis=1)
+    first_sorted = np.ones_like(S, dtype=bool)
+    first_sorted[:, 1:] = S[:, 1:] != S[:, :-1]
+    first_sorted &= S >= 0
+    F = np.zeros_like(first_sorted)
+    np.put_along_axis(F, order, first_sorted, axis=1)
+    C = np.cumsum(F, axis=1)
+    keep = F & (C <= nnz[:, None])
+    out = np.where(keep, D, vocab)
+    out.sort(axis=1)
+    return out, C[:, -1] >= nnz
+
+
 def _zipf_rows(rng, m, mean_extra, vocab, zipf_a, sigma):
-    """m sparse rows; nnz = 1 + Poisson(mean_extra), ids distinct, id-sorted."""
-    nnz = 1 + rng.poisson(mean_extra, size=m)
-    nnz = np.minimum(nnz, vocab)
+    """m sparse rows; nnz = 1 + Poisson(mean_extra), ids distinct, id-sorted.
+
+    Each row takes, in draw order, the first nnz distinct ids among draws of
+    Zipf(zipf_a) truncated to the vocabulary (rank r -> id r - 1).  Draws are
+    made in blocks of columns; rows that are still short draw another block.
+    """
+    nnz = np.minimum(1 + rng.poisson(mean_extra, size=m), vocab)
+    width = int(4 * nnz.max()) + 16 if m else 1
+    D = rng.zipf(zipf_a, size=(m, width))
+    D = np.where(D <= vocab, D - 1, -1).astype(np.int64)
+    best, ok = _first_distinct(D, nnz, vocab)
+    short = np.flatnonzero(~ok)
+    while short.size:
+        more = rng.zipf(zipf_a, size=(short.size, width))
+        more = np.where(more <= vocab, more - 1, -1).astype(np.int64)
+        Ds = np.concatenate([D[short], more], axis=1)
+        b2, ok2 = _first_distinct(Ds, nnz[short], vocab)
+        cols = min(best.shape[1], b2.shape[1])
+        best[short, :cols] = b2[:, :cols]
+        D = np.pad(D, ((0, 0), (0, width)), constant_values=-1)
+        D[short] = Ds
+        short = short[~ok2]
     indptr = np.zeros(m + 1, dtype=np.int64)
     np.cumsum(nnz, out=indptr[1:])
-    ids = np.empty(int(indptr[-1]), dtype=np.uint16)
-    for r in range(m):
-        need = int(nnz[r])
-        got = np.empty(0, dtype=np.int64)
-        while got.size < need:
-            draw = rng.zipf(zipf_a, size=2 * (need - got.size) + 8)
-            draw = draw[draw <= vocab] - 1
-            # keep first occurrences, in draw order, until `need` distinct ids
-            got = np.concatenate([got, draw])
-            _, first = np.unique(got, return_index=True)
-            got = got[np.sort(first)]
-        ids[indptr[r]:indptr[r + 1]] = np.sort(got[:need])
+    take = np.arange(best.shape[1])[None, :] < nnz[:, None]
+    ids = best[take].astype(np.uint16)
     vals = np.exp(sigma * rng.standard_normal(int(indptr[-1]))).astype(np.float32)
     return indptr, ids, vals
 

@@ -37,12 +37,18 @@ def big():
     X = synth.dense_base(spec)
     Q = synth.dense_queries(spec)
     X16 = X.astype(np.float16).view(np.uint16)   # equals oracle.to_f16 (pinned on the CPU)
+    f8, s8 = oracle.encode_fp8_rows(X)
+    cb = codes = None
+    if os.path.exists(os.path.join(DATA, "pq.npz")):
+        z = np.load(os.path.join(DATA, "pq.npz"))
+        cb, codes = z["codebook"], z["codes"]
     say("uploading")
-    ix = ann.ann_index_create(g, "ip", X.shape[1], x_f32=X, x_f16=X16)
+    ix = ann.ann_index_create(g, "ip", X.shape[1], x_f32=X, x_f16=X16, x_fp8=f8, fp8_scale=s8,
+                              pq_codebook=cb, pq_codes=codes)
     gt = None
     if os.path.exists(os.path.join(DATA, "gt.npz")):
         gt = np.load(os.path.join(DATA, "gt.npz"))["ids"]
-    yield dict(g=g, X=X, X16=X16, Q=Q, ix=ix, gt=gt)
+    yield dict(g=g, X=X, X16=X16, f8=f8, s8=s8, cb=cb, codes=codes, Q=Q, ix=ix, gt=gt)
     ix.close()
 
 
@@ -93,12 +99,39 @@ def test_full_batch_sampled_bitexact(big, mode):
 
 
 def test_maximum_ef(big):
-    say("ef = 4096 on 6 queries")
+    ef = ann.ANN_EF_MAX
+    say("ef =", ef, "on 6 queries")
     Q = big["Q"][:6]
     r = ann.ann_search_ex(big["ix"], "f16", queries=torch.from_numpy(Q).to("cuda:0"), k=10,
-                          ef=4096, rerank=40, want_stats=True)
+                          ef=ef, rerank=40, want_stats=True)
     torch.cuda.synchronize()
-    ref = oracle.hnsw_search(big["g"], oracle.dense_store(big["X16"], "ip", "f16"), 10, 4096, Q=Q,
+    ref = oracle.hnsw_search(big["g"], oracle.dense_store(big["X16"], "ip", "f16"), 10, ef, Q=Q,
                              rerank_f32=big["X"], rerank=40)
     assert np.array_equal(r["ids"].cpu().numpy(), ref["ids"])
     assert np.array_equal(r["stats"].cpu().numpy()[:, 2], ref["stats"][:, 3])
+
+
+@pytest.mark.parametrize("mode", ["pq", "fp8"])
+def test_quantized_traversal_with_rerank(big, mode):
+    """PQ (64 x 256, ADC tables in LDS) and FP8-E4M3 traversal, FP32 rerank of
+    the first 100 beam entries, on the graph built on the FP32 originals."""
+    if mode == "pq" and big["codes"] is None:
+        pytest.skip("data/vmf1m/pq.npz not built (python -m oracle.build_index vmf1m --what pq)")
+    ef = 400
+    say(mode, "ef", ef, "rerank 100, all 10,000 queries")
+    q = torch.from_numpy(big["Q"]).to("cuda:0")
+    r = ann.ann_search_ex(big["ix"], mode, queries=q, k=10, ef=ef, rerank=100, want_stats=True)
+    torch.cuda.synchronize()
+    ids, dists, stats = (r[k].cpu().numpy() for k in ("ids", "dists", "stats"))
+    sample = np.random.default_rng(1).choice(big["Q"].shape[0], 32, replace=False)
+    if mode == "pq":
+        st = oracle.pq_store(big["cb"], big["codes"], "ip")
+    else:
+        st = oracle.dense_store(big["f8"], "ip", "fp8", fp8_scale=big["s8"])
+    ref = oracle.hnsw_search(big["g"], st, 10, ef, Q=big["Q"][sample], rerank_f32=big["X"],
+                             rerank=100)
+    assert np.array_equal(ids[sample], ref["ids"])
+    assert np.array_equal(dists[sample], ref["keys"])
+    assert np.array_equal(stats[sample, 2], ref["stats"][:, 3])
+    if big["gt"] is not None:
+        say(mode, "recall@10", oracle.recall_at_k(ids, big["gt"], 10))
