@@ -227,14 +227,19 @@ int ann_search_sparse(const ann_index* ix, const int64_t* q_indptr, const uint16
 /* ---- launch configuration ------------------------------------------------ */
 
 /*
- * The traversal kernel is persistent: `slots` one-wavefront workgroups pull
- * query indices from a device counter.  lanes_per_row (16, 32 or 64) is how
- * many lanes evaluate one dense row together.  Zeros select the built-in
- * defaults (or the autotuned values, once ann_autotune has run).
+ * The traversal kernel is persistent: `slots` workgroups pull query indices
+ * from a device counter, one query per workgroup at a time.  A workgroup has
+ * waves_per_query wavefronts (1, 2 or 4): they share the query's beam in LDS
+ * and split the row gathers of each expansion, so a large beam (whose LDS
+ * limits the queries per compute unit) still keeps many rows in flight.
+ * lanes_per_row (16, 32 or 64) is how many lanes evaluate one dense row
+ * together.  Zeros select the built-in defaults (or the autotuned values,
+ * once ann_autotune has run).  Results do not depend on these settings.
  */
 typedef struct ann_launch_cfg {
   int32_t slots;
   int32_t lanes_per_row;
+  int32_t waves_per_query;
 } ann_launch_cfg;
 
 int ann_set_launch(ann_index* ix, int32_t mode, const ann_launch_cfg* cfg);

@@ -56,7 +56,7 @@ class AnnBatch(C.Structure):
 
 
 class AnnLaunchCfg(C.Structure):
-    _fields_ = [("slots", I32), ("lanes_per_row", I32)]
+    _fields_ = [("slots", I32), ("lanes_per_row", I32), ("waves_per_query", I32)]
 
 
 class AnnServerCfg(C.Structure):
@@ -307,8 +307,8 @@ def ann_search_sparse(index, indptr, ids, vals, k, ef):
     return out_ids, out_d
 
 
-def ann_set_launch(index, mode, slots=0, lanes_per_row=0):
-    cfg = AnnLaunchCfg(int(slots), int(lanes_per_row))
+def ann_set_launch(index, mode, slots=0, lanes_per_row=0, waves_per_query=0):
+    cfg = AnnLaunchCfg(int(slots), int(lanes_per_row), int(waves_per_query))
     _check(lib().ann_set_launch(index.handle, MODE[mode] if isinstance(mode, str) else int(mode),
                                 C.byref(cfg)))
 
@@ -317,7 +317,8 @@ def ann_get_launch(index, mode):
     cfg = AnnLaunchCfg()
     _check(lib().ann_get_launch(index.handle, MODE[mode] if isinstance(mode, str) else int(mode),
                                 C.byref(cfg)))
-    return {"slots": cfg.slots, "lanes_per_row": cfg.lanes_per_row}
+    return {"slots": cfg.slots, "lanes_per_row": cfg.lanes_per_row,
+            "waves_per_query": cfg.waves_per_query}
 
 
 def ann_autotune(index, mode="f32", queries=None, sparse=None, k=10, ef=64, rerank=0):
@@ -337,7 +338,8 @@ def ann_autotune(index, mode="f32", queries=None, sparse=None, k=10, ef=64, rera
     b.out_ids, b.out_dists = _dptr(ids), _dptr(dists)
     cfg = AnnLaunchCfg()
     _check(lib().ann_autotune(index.handle, C.byref(b), C.byref(cfg)))
-    return {"slots": cfg.slots, "lanes_per_row": cfg.lanes_per_row}
+    return {"slots": cfg.slots, "lanes_per_row": cfg.lanes_per_row,
+            "waves_per_query": cfg.waves_per_query}
 
 
 def ann_bruteforce(index, queries, k, stream=None):

@@ -145,6 +145,8 @@ int validate_graph(const ann_index_desc* D) {
 
 namespace ann {
 
+int default_waves(const ann_index* ix, const SearchParams& P);
+
 int ensure_workspace(ann_index* ix, Workspace& ws, int64_t slots) {
   if (ws.slots >= slots && ws.device == ix->device) return ANN_OK;
   if (ws.done) HIP_OR_RETURN(hipEventSynchronize(ws.done), "hipEventSynchronize");
@@ -206,6 +208,7 @@ int make_params(const ann_index* ix, const ann_batch* b, SearchParams* P) {
   } else {
     P->lanes_per_row = 64;
   }
+  P->waves_per_query = cfg.waves_per_query ? cfg.waves_per_query : 1;
   P->fp8_scale = ix->fp8_scale;
   P->pq_cb = ix->pq_cb;
   P->pq_codes = ix->pq_codes;
@@ -246,14 +249,32 @@ int make_params(const ann_index* ix, const ann_batch* b, SearchParams* P) {
   if (lds_bytes(*P) > ix->lds_limit)
     return fail(ANN_EBUDGET, "on-chip memory for ef %d in mode %d: %zu bytes > %zu", ef_cap, mode,
                 lds_bytes(*P), ix->lds_limit);
+  if (!cfg.waves_per_query) P->waves_per_query = default_waves(ix, *P);
   return ANN_OK;
+}
+
+// More waves per query when the beam's LDS, not the registers, bounds how
+// many queries a compute unit holds: the spare wave slots then gather rows
+// for the resident queries.
+int default_waves(const ann_index* ix, const SearchParams& P) {
+  const void* fn = kernel_symbol(P);
+  if (!fn) return 1;
+  int with_lds = 0, without = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&with_lds, fn, 64, lds_bytes(P)) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&without, fn, 64, 0) != hipSuccess || with_lds < 1)
+    return 1;
+  (void)ix;
+  const int ratio = without / with_lds;
+  return ratio >= 4 ? 4 : ratio >= 2 ? 2 : 1;
 }
 
 int64_t pick_slots(const ann_index* ix, const SearchParams& P, int64_t requested) {
   int per_cu = 0;
   const void* fn = kernel_symbol(P);
   size_t lds = lds_bytes(P);
-  if (fn && hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, lds) != hipSuccess) per_cu = 0;
+  if (fn && hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * P.waves_per_query, lds) !=
+                hipSuccess)
+    per_cu = 0;
   if (per_cu <= 0) per_cu = 4;
   int64_t slots = requested > 0 ? requested : (int64_t)ix->cu_count * per_cu;
   // bound the visited bitsets to 4 GiB
@@ -472,6 +493,9 @@ int ann_set_launch(ann_index* ix, int32_t mode, const ann_launch_cfg* cfg) {
   if (!ix || !cfg) return fail(ANN_EINVAL, "NULL argument");
   if (mode < 0 || mode > ANN_MODE_SPARSE) return fail(ANN_EINVAL, "unknown mode");
   if (cfg->slots < 0) return fail(ANN_EINVAL, "slots < 0");
+  if (cfg->waves_per_query != 0 && cfg->waves_per_query != 1 && cfg->waves_per_query != 2 &&
+      cfg->waves_per_query != 4)
+    return fail(ANN_EINVAL, "waves_per_query must be 0, 1, 2 or 4");
   if (cfg->lanes_per_row != 0) {
     if (!is_dense(mode)) return fail(ANN_EINVAL, "lanes_per_row applies to dense modes");
     if (!dense_shape_supported(mode, ix->d * elem_bytes(mode) / 16, cfg->lanes_per_row))
@@ -500,7 +524,8 @@ int ann_autotune(ann_index* ix, const ann_batch* b, ann_launch_cfg* best) {
   std::vector<int> lanes = is_dense(b->mode) ? std::vector<int>{16, 32, 64} : std::vector<int>{0};
   for (int L : lanes) {
     if (L && !dense_shape_supported(b->mode, P.nchunks, L)) continue;
-    for (int mult : {1, 2, 4, 8, 16}) cands.push_back(ann_launch_cfg{ix->cu_count * mult, L});
+    for (int nw : {1, 2, 4})
+      for (int mult : {1, 2, 4, 8, 16}) cands.push_back(ann_launch_cfg{ix->cu_count * mult, L, nw});
   }
   std::lock_guard<std::mutex> lock(ix->mu);
   hipEvent_t e0, e1;
@@ -511,6 +536,7 @@ int ann_autotune(ann_index* ix, const ann_batch* b, ann_launch_cfg* best) {
   for (const ann_launch_cfg& c : cands) {
     SearchParams Q = P;
     if (c.lanes_per_row) Q.lanes_per_row = c.lanes_per_row;
+    Q.waves_per_query = c.waves_per_query;
     if (lds_bytes(Q) > ix->lds_limit) continue;
     float ms = 0.f;
     for (int rep = 0; rep < 2; ++rep) {  // first run warms caches

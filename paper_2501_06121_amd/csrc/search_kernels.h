@@ -12,6 +12,7 @@ enum { METRIC_L2 = 0, METRIC_IP = 1 };
 struct SearchParams {
   int mode, metric;
   int d, nchunks, lanes_per_row;
+  int waves_per_query;              // wavefronts of one workgroup (1, 2 or 4)
   // representation searched
   const void* rows;
   const float* fp8_scale;

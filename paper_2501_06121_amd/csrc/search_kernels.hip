@@ -46,7 +46,18 @@ constexpr uint32_t kHashEmpty = 0xFFFFFFFFu;
 // small helpers
 // ----------------------------------------------------------------------------
 
-__device__ __forceinline__ int lane_id() { return (int)threadIdx.x; }
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+__device__ __forceinline__ int wave_id() { return (int)(threadIdx.x >> 6); }
+__device__ __forceinline__ int num_waves() { return (int)(blockDim.x >> 6); }
+
+// Ordering point inside one wavefront: its LDS instructions execute in issue
+// order, and the fence keeps the compiler from moving accesses across.  Used
+// where only one wave of the workgroup runs (the other waves wait at a
+// workgroup barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
@@ -112,7 +123,11 @@ struct Lds {
   float* hval;       // [kHashSlots]
   int64_t* sb;       // [64] sparse row extents of one expansion
   int64_t* se;       // [64]
+  int32_t* ctl;      // [16] values wave 0 publishes to the other waves
 };
+
+enum { CTL_QUERY = 0, CTL_M = 1, CTL_W = 2, CTL_HINT = 3, CTL_VISITED = 4, CTL_VLOG = 5,
+       CTL_VLOG_OVF = 6 };
 
 // Rerank keys held at once: R_eff <= min(max(R, k_max), ef_cap).
 __host__ __device__ inline int rerank_slots(const SearchParams& p) {
@@ -137,6 +152,7 @@ __device__ Lds carve(char* base, const SearchParams& p) {
   s.hval = (float*)take(sizeof(float) * (p.mode == MODE_SPARSE ? kHashSlots : 0));
   s.sb = (int64_t*)take(sizeof(int64_t) * (p.mode == MODE_SPARSE ? 64 : 0));
   s.se = (int64_t*)take(sizeof(int64_t) * (p.mode == MODE_SPARSE ? 64 : 0));
+  s.ctl = (int32_t*)take(sizeof(int32_t) * 16);
   return s;
 }
 
@@ -216,13 +232,17 @@ struct Dense {
     const int grp = lane / L;
     const size_t row_bytes = (size_t)p.nchunks * 16;
     const char* rows = (const char*)p.rows;
-    for (int base = 0; base < m; base += G * U) {
+    // the waves of the workgroup take contiguous shares of the rows
+    const int per = (m + num_waves() - 1) / num_waves();
+    const int lo = wave_id() * per;
+    const int hi = lo + per < m ? lo + per : m;
+    for (int base = lo; base < hi; base += G * U) {
       uint4 raw[U][CPL];
       int rid[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int ci = base + u * G + grp;
-        rid[u] = (ci < m) ? s.cid[ci] : -1;
+        rid[u] = (ci < hi) ? s.cid[ci] : -1;
         const char* rp = rows + (size_t)(rid[u] < 0 ? 0 : rid[u]) * row_bytes;
 #pragma unroll
         for (int t = 0; t < CPL; ++t) {
@@ -235,7 +255,7 @@ struct Dense {
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        if (base + u * G >= m) break;
+        if (base + u * G >= hi) break;
         const float scale = (MODE == MODE_FP8 && rid[u] >= 0) ? p.fp8_scale[rid[u]] : 1.0f;
         float acc[V];
 #pragma unroll
@@ -253,7 +273,7 @@ struct Dense {
         // levels s = L/2 .. 1 across the lanes of the group
         float val = fold_lanes<L>(acc[0]);
         const int ci = base + u * G + grp;
-        if (j == 0 && ci < m) {
+        if (j == 0 && ci < hi) {
           float key;
           if constexpr (IP) {
             if constexpr (MODE == MODE_FP8) val = scale * val;
@@ -279,11 +299,10 @@ struct Dense {
 
 struct PQ {
   __device__ bool prep(const SearchParams& p, const Lds& s, int64_t q) {
-    const int lane = lane_id();
     const int ds = p.pq_dsub;
     const int entries = p.pq_m * 256;
     const bool ip = p.metric == METRIC_IP;
-    for (int e = lane; e < entries; e += 64) {
+    for (int e = threadIdx.x; e < entries; e += blockDim.x) {
       const int m = e >> 8;
       const float* c = p.pq_cb + (size_t)e * ds;
       const float* qs = s.q + m * ds;
@@ -303,9 +322,10 @@ struct PQ {
   }
 
   __device__ void score(const SearchParams& p, const Lds& s, int m) {
-    const int lane = lane_id();
-    if (lane < m) {
-      const int64_t r = s.cid[lane];
+    const int per = (m + num_waves() - 1) / num_waves();
+    const int ci = wave_id() * per + lane_id();
+    if (lane_id() < per && ci < m) {
+      const int64_t r = s.cid[ci];
       const uint4* cp = (const uint4*)(p.pq_codes + (size_t)r * p.pq_stride);
       float part[64];
       uint4 w4[4];
@@ -323,7 +343,7 @@ struct PQ {
       for (int h = 32; h >= 1; h >>= 1)
 #pragma unroll
         for (int v = 0; v < h; ++v) part[v] = part[v] + part[v + h];
-      s.ckey[lane] = (p.metric == METRIC_IP) ? -part[0] : part[0];
+      s.ckey[ci] = (p.metric == METRIC_IP) ? -part[0] : part[0];
     }
   }
 };
@@ -339,14 +359,13 @@ __device__ __forceinline__ uint32_t hash_slot(uint32_t t) {
 
 struct Sparse {
   __device__ bool prep(const SearchParams& p, const Lds& s, int64_t q) {
-    const int lane = lane_id();
-    for (int i = lane; i < kHashSlots; i += 64) { s.hkey[i] = kHashEmpty; s.hval[i] = 0.0f; }
+    for (int i = threadIdx.x; i < kHashSlots; i += blockDim.x) { s.hkey[i] = kHashEmpty; s.hval[i] = 0.0f; }
     __syncthreads();
     const int64_t b = p.q_ptr[q];
     int64_t e = p.q_ptr[q + 1];
     const bool ok = e - b <= kHashSlots / 2;
     if (!ok) e = b + kHashSlots / 2;     // keeps the table at most half full
-    for (int64_t j = b + lane; j < e; j += 64) {
+    for (int64_t j = b + threadIdx.x; j < e; j += blockDim.x) {
       const uint32_t t = p.q_ids[j];
       const float w = p.q_vals[j];
       uint32_t h = hash_slot(t);
@@ -374,13 +393,16 @@ struct Sparse {
     const int lane = lane_id();
     constexpr int U = 8;   // documents in flight
     // every candidate's extent in one round trip
-    if (lane < m) {
-      const int64_t r = s.cid[lane];
-      s.sb[lane] = p.sp_ptr[r];
-      s.se[lane] = p.sp_ptr[r + 1];
+    if ((int)threadIdx.x < m) {
+      const int64_t r = s.cid[threadIdx.x];
+      s.sb[threadIdx.x] = p.sp_ptr[r];
+      s.se[threadIdx.x] = p.sp_ptr[r + 1];
     }
     __syncthreads();
-    for (int base = 0; base < m; base += U) {
+    const int per = (m + num_waves() - 1) / num_waves();
+    const int lo = wave_id() * per;
+    const int hi = lo + per < m ? lo + per : m;
+    for (int base = lo; base < hi; base += U) {
       float acc[U];
       int64_t b[U], e[U];
       int64_t most = 0;
@@ -388,8 +410,8 @@ struct Sparse {
       for (int u = 0; u < U; ++u) {
         acc[u] = 0.0f;
         const int ci = base + u;
-        b[u] = (ci < m) ? s.sb[ci] : 0;
-        e[u] = (ci < m) ? s.se[ci] : 0;
+        b[u] = (ci < hi) ? s.sb[ci] : 0;
+        e[u] = (ci < hi) ? s.se[ci] : 0;
         most = (e[u] - b[u] > most) ? e[u] - b[u] : most;
       }
       for (int64_t off = lane; off < most; off += 64) {
@@ -407,7 +429,7 @@ struct Sparse {
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        if (base + u >= m) break;
+        if (base + u >= hi) break;
         const float val = fold_lanes<64>(acc[u]);
         if (lane == 0) s.ckey[base + u] = -val;
       }
@@ -468,7 +490,7 @@ __device__ int merge_into_w(const Lds& s, int w, int ef, int mnew, float k, uint
     r = rank_in_w(s, w, k, id);
     s.rnk[lane] = r;
   }
-  __syncthreads();
+  wave_sync();
   const int r0 = uniform_int(__shfl(r, 0, 64));
   // shift the tail [r0, w) up by the number of new entries ranked at or below
   // each position; highest chunk first so no unread entry is overwritten
@@ -495,16 +517,16 @@ __device__ int merge_into_w(const Lds& s, int w, int ef, int mnew, float k, uint
         }
         dest = j + cnt;
       }
-      __syncthreads();
+      wave_sync();
       if (j < w && dest < ef) { s.wkey[dest] = wk; s.wid[dest] = wi; }
-      __syncthreads();
+      wave_sync();
     }
   }
   if (lane < mnew) {
     const int pos = r + lane;
     if (pos < ef) { s.wkey[pos] = k; s.wid[pos] = id; }
   }
-  __syncthreads();
+  wave_sync();
   *first_pos = (mnew > 0) ? r0 : 0x7FFFFFFF;
   const int nw = w + mnew;
   return nw < ef ? nw : ef;
@@ -538,6 +560,9 @@ __device__ __forceinline__ void log_visited(const SearchParams& p, int slot, int
 template <class Policy>
 __device__ void run_query(const SearchParams& p, const Lds& s, Policy& pol, int slot, int64_t q) {
   const int lane = lane_id();
+  const int wave = wave_id();
+  const int tid = threadIdx.x;
+  const int nthr = blockDim.x;
   int k = p.k_arr ? p.k_arr[q] : p.k_all;
   int ef = p.ef_arr ? p.ef_arr[q] : p.ef_all;
   int status = 0;
@@ -551,24 +576,26 @@ __device__ void run_query(const SearchParams& p, const Lds& s, Policy& pol, int 
   // FP32 query copy in LDS for the rerank and the PQ tables
   if (p.q_lds_floats > 0 && p.queries) {
     const float* qrow = p.queries + (size_t)q * p.d;
-    for (int i = lane; i < p.q_lds_floats; i += 64) s.q[i] = (i < p.d) ? qrow[i] : 0.0f;
+    for (int i = tid; i < p.q_lds_floats; i += nthr) s.q[i] = (i < p.d) ? qrow[i] : 0.0f;
   }
   __syncthreads();
   if (!pol.prep(p, s, q)) status |= 2;
 
+  // Wave 0 owns the visited bits and the log; every wave counts evaluations.
   QueryState st{0, 0, 0, 0, false};
   uint32_t* bits = p.bits + (size_t)slot * p.bits_words;
 
   // entry point
   int cur = p.entry;
-  if (lane == 0) s.cid[0] = cur;
+  if (tid == 0) s.cid[0] = cur;
   __syncthreads();
   pol.score(p, s, 1);
   __syncthreads();
   float ckey = s.ckey[0];
   st.evals += 1;
 
-  // greedy descent, layers max_level .. 1
+  // greedy descent, layers max_level .. 1 (every wave computes the same
+  // neighbour list and minimum; the rows are scored by all waves)
   for (int lc = p.max_level; lc >= 1; --lc) {
     while (true) {
       const int off = p.upper_off[cur];
@@ -601,14 +628,14 @@ __device__ void run_query(const SearchParams& p, const Lds& s, Policy& pol, int 
   }
 
   // layer 0
-  {
+  if (wave == 0) {
     const uint32_t bit = 1u << (cur & 31);
     uint32_t old = 0;
     if (lane == 0) old = atomicOr(&bits[cur >> 5], bit);
     const bool isnew = (lane == 0) && !(old & bit);
     log_visited(p, slot, q, st, isnew, cur, ballot(isnew));
   }
-  if (lane == 0) { s.wkey[0] = ckey; s.wid[0] = (uint32_t)cur; }
+  if (tid == 0) { s.wkey[0] = ckey; s.wid[0] = (uint32_t)cur; }
   __syncthreads();
   int w = 1;
   int hint = 0;
@@ -617,65 +644,80 @@ __device__ void run_query(const SearchParams& p, const Lds& s, Policy& pol, int 
     if (cpos < 0) break;
     const int c = (int)(s.wid[cpos] & kIdMask);
     __syncthreads();
-    if (lane == 0) s.wid[cpos] = (uint32_t)c | kExpanded;
+    if (tid == 0) s.wid[cpos] = (uint32_t)c | kExpanded;
     hint = cpos + 1;
     st.expansions += 1;
-    int nb = (lane < p.M0) ? p.adj0[(size_t)c * p.M0 + lane] : -1;
-    bool isnew = false;
-    if (nb >= 0) {
-      const uint32_t bit = 1u << (nb & 31);
-      const uint32_t old = atomicOr(&bits[nb >> 5], bit);
-      isnew = !(old & bit);
+    if (wave == 0) {
+      // neighbour list, visited bits (each bit set exactly once), compaction
+      const int nb = (lane < p.M0) ? p.adj0[(size_t)c * p.M0 + lane] : -1;
+      bool isnew = false;
+      if (nb >= 0) {
+        const uint32_t bit = 1u << (nb & 31);
+        const uint32_t old = atomicOr(&bits[nb >> 5], bit);
+        isnew = !(old & bit);
+      }
+      const uint64_t mk = ballot(isnew);
+      log_visited(p, slot, q, st, isnew, nb, mk);
+      if (isnew) s.cid[mbcnt(mk)] = nb;
+      if (lane == 0) s.ctl[CTL_M] = __builtin_popcountll(mk);
     }
-    const uint64_t mk = ballot(isnew);
-    const int m = __builtin_popcountll(mk);
-    log_visited(p, slot, q, st, isnew, nb, mk);
-    if (m == 0) { __syncthreads(); continue; }
-    if (isnew) s.cid[mbcnt(mk)] = nb;
     __syncthreads();
+    const int m = s.ctl[CTL_M];
+    if (m == 0) continue;
     pol.score(p, s, m);
     __syncthreads();
     st.evals += m;
-    float kk = __builtin_inff();
-    uint32_t ki = kIdMask;
-    bool keep = false;
-    if (lane < m) {
-      kk = s.ckey[lane];
-      ki = (uint32_t)s.cid[lane];
-      keep = (w < ef) || kid_lt(kk, ki, s.wkey[ef - 1], s.wid[ef - 1] & kIdMask);
-    }
-    const uint64_t km = ballot(keep);
-    const int mnew = __builtin_popcountll(km);
-    if (mnew == 0) { __syncthreads(); continue; }
-    // compact the kept entries to lanes [0, mnew), then sort the smallest
-    // power-of-two prefix that holds them
-    if (km != (~0ull >> (64 - mnew))) {
-      __syncthreads();
-      if (keep) { s.ckey[mbcnt(km)] = kk; s.cid[mbcnt(km)] = (int32_t)ki; }
-      __syncthreads();
-      kk = (lane < mnew) ? s.ckey[lane] : __builtin_inff();
-      ki = (lane < mnew) ? (uint32_t)s.cid[lane] : kIdMask;
-    }
-    if (mnew > 1) {
-      int sz = 2;
-      while (sz < mnew) sz <<= 1;
-      if (lane >= mnew) { kk = __builtin_inff(); ki = kIdMask; }
-      sort_lanes(kk, ki, sz);
+    if (wave == 0) {
+      float kk = __builtin_inff();
+      uint32_t ki = kIdMask;
+      bool keep = false;
+      if (lane < m) {
+        kk = s.ckey[lane];
+        ki = (uint32_t)s.cid[lane];
+        keep = (w < ef) || kid_lt(kk, ki, s.wkey[ef - 1], s.wid[ef - 1] & kIdMask);
+      }
+      const uint64_t km = ballot(keep);
+      const int mnew = __builtin_popcountll(km);
+      if (mnew > 0) {
+        // compact the kept entries to lanes [0, mnew), then sort the smallest
+        // power-of-two prefix that holds them
+        if (km != (~0ull >> (64 - mnew))) {
+          wave_sync();
+          if (keep) { s.ckey[mbcnt(km)] = kk; s.cid[mbcnt(km)] = (int32_t)ki; }
+          wave_sync();
+          kk = (lane < mnew) ? s.ckey[lane] : __builtin_inff();
+          ki = (lane < mnew) ? (uint32_t)s.cid[lane] : kIdMask;
+        }
+        if (mnew > 1) {
+          int sz = 2;
+          while (sz < mnew) sz <<= 1;
+          if (lane >= mnew) { kk = __builtin_inff(); ki = kIdMask; }
+          sort_lanes(kk, ki, sz);
+        }
+        int first_pos;
+        w = merge_into_w(s, w, ef, mnew, kk, ki, &first_pos);
+        if (first_pos < hint) hint = first_pos;
+      }
+      if (lane == 0) { s.ctl[CTL_W] = w; s.ctl[CTL_HINT] = hint; }
     }
     __syncthreads();
-    int first_pos;
-    w = merge_into_w(s, w, ef, mnew, kk, ki, &first_pos);
-    if (first_pos < hint) hint = first_pos;
+    w = s.ctl[CTL_W];
+    hint = s.ctl[CTL_HINT];
+  }
+  if (wave == 0 && lane == 0) {
+    s.ctl[CTL_VISITED] = st.visited;
+    s.ctl[CTL_VLOG] = st.vlog_n;
+    s.ctl[CTL_VLOG_OVF] = st.vlog_overflow ? 1 : 0;
   }
 
-  // rerank with the FP32 rows
+  // rerank with the FP32 rows (rows split across the waves)
   int nres = w;
   if (p.rerank > 0) {
     int R = p.rerank > k ? p.rerank : k;
     if (R > w) R = w;
     nres = R;
     const int nch = p.d / 4;   // FP32 chunks
-    for (int i0 = 0; i0 < R; i0 += 4) {
+    for (int i0 = 4 * wave; i0 < R; i0 += 4 * num_waves()) {
       // four rows at a time, 64 lanes per row
       uint4 raw[4][4];
       int rid[4];
@@ -721,7 +763,7 @@ __device__ void run_query(const SearchParams& p, const Lds& s, Policy& pol, int 
     }
     __syncthreads();
     // rank by (key, id) and write the first k
-    for (int i = lane; i < R; i += 64) {
+    for (int i = tid; i < R; i += nthr) {
       const float ki = s.rk[i];
       const uint32_t ii = s.wid[i] & kIdMask;
       int rank = 0;
@@ -732,52 +774,57 @@ __device__ void run_query(const SearchParams& p, const Lds& s, Policy& pol, int 
       }
     }
   } else {
-    for (int i = lane; i < k && i < w; i += 64) {
+    for (int i = tid; i < k && i < w; i += nthr) {
       p.out_ids[q * p.k_max + i] = (int64_t)(s.wid[i] & kIdMask);
       p.out_dists[q * p.k_max + i] = s.wkey[i];
     }
   }
-  for (int i = lane; i < p.k_max; i += 64) {
+  __syncthreads();
+  const int visited = s.ctl[CTL_VISITED];
+  const int vlog_n = s.ctl[CTL_VLOG];
+  const bool vlog_ovf = s.ctl[CTL_VLOG_OVF] != 0;
+  for (int i = tid; i < p.k_max; i += nthr) {
     if (i >= k || i >= nres) {
       p.out_ids[q * p.k_max + i] = -1;
       p.out_dists[q * p.k_max + i] = __builtin_inff();
     }
   }
-  if (lane == 0) {
+  if (tid == 0) {
     if (p.out_status) p.out_status[q] = status;
     if (p.out_stats) {
       p.out_stats[q * 4 + 0] = st.evals;
       p.out_stats[q * 4 + 1] = st.expansions;
-      p.out_stats[q * 4 + 2] = st.visited;
+      p.out_stats[q * 4 + 2] = visited;
       p.out_stats[q * 4 + 3] = w;
     }
   }
   if (p.out_visited) {
-    for (int64_t i = st.visited + lane; i < p.visited_cap; i += 64) p.out_visited[q * p.visited_cap + i] = -1;
+    for (int64_t i = visited + tid; i < p.visited_cap; i += nthr) p.out_visited[q * p.visited_cap + i] = -1;
   }
 
   // leave the slot's visited bits clear for the next query
-  if (!st.vlog_overflow) {
+  if (!vlog_ovf) {
     const int32_t* lg = p.vlog + (size_t)slot * p.vlog_cap;
-    for (int i = lane; i < st.vlog_n; i += 64) bits[lg[i] >> 5] = 0u;
+    for (int i = tid; i < vlog_n; i += nthr) bits[lg[i] >> 5] = 0u;
   } else {
-    for (int64_t i = lane; i < p.bits_words; i += 64) bits[i] = 0u;
+    for (int64_t i = tid; i < p.bits_words; i += nthr) bits[i] = 0u;
   }
   __threadfence();
   __syncthreads();
 }
 
 template <class Policy>
-__global__ void __launch_bounds__(64) search_kernel(SearchParams p) {
+__global__ void __launch_bounds__(256) search_kernel(SearchParams p) {
   extern __shared__ __align__(16) char lds_raw[];
   const Lds s = carve(lds_raw, p);
   Policy pol;
   const int slot = blockIdx.x;
   const int64_t nq = p.nq_dev ? (int64_t)uniform_int(*p.nq_dev) : p.nq;
   while (true) {
-    int qi = 0;
-    if (lane_id() == 0) qi = atomicAdd(p.counter, 1);
-    qi = uniform_int(__shfl(qi, 0, 64));
+    if (threadIdx.x == 0) s.ctl[CTL_QUERY] = atomicAdd(p.counter, 1);
+    __syncthreads();
+    const int qi = uniform_int(s.ctl[CTL_QUERY]);
+    __syncthreads();
     if (qi >= nq) break;
     run_query(p, s, pol, slot, (int64_t)qi);
   }
@@ -792,7 +839,7 @@ __global__ void reset_counter_kernel(int32_t* c) { *c = 0; }
 template <class Policy>
 static hipError_t launch(const SearchParams& p, int slots, size_t lds, hipStream_t st) {
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, p.counter);
-  hipLaunchKernelGGL(search_kernel<Policy>, dim3(slots), dim3(64), lds, st, p);
+  hipLaunchKernelGGL(search_kernel<Policy>, dim3(slots), dim3(64 * p.waves_per_query), lds, st, p);
   return hipGetLastError();
 }
 
@@ -848,6 +895,7 @@ size_t lds_bytes(const SearchParams& p) {
   b += al(p.mode == MODE_PQ ? 4 * (size_t)p.pq_m * 256 : 0);
   b += al(p.mode == MODE_SPARSE ? 4 * kHashSlots : 0) * 2;
   b += al(p.mode == MODE_SPARSE ? 8 * 64 : 0) * 2;
+  b += al(4 * 16);
   return b;
 }
 

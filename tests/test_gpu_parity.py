@@ -223,3 +223,60 @@ def test_ann_search_blocking_api(c1):
     ref = oracle.hnsw_search(c1["g"], oracle.dense_store(c1["X"], "l2"), 10, 64, Q=c1["Q"])
     assert np.array_equal(ids.cpu().numpy(), ref["ids"])
     assert np.array_equal(d.cpu().numpy(), ref["keys"])
+
+
+@pytest.mark.parametrize("waves", [2, 4])
+def test_waves_per_query_do_not_change_results(c1, v768, sparse_small, waves):
+    say("waves per query", waves)
+    # dense L2, with and without rerank
+    for mode, rr in (("f32", 0), ("f16", 40)):
+        st = store_for(c1, mode, "l2")
+        ref = oracle.hnsw_search(c1["g"], st, 10, 200, Q=c1["Q"], rerank_f32=c1["X"] if rr else None,
+                                 rerank=rr, visited_cap=4096)
+        ann.ann_set_launch(c1["ix"], mode, waves_per_query=waves)
+        try:
+            got = gpu(c1["ix"], mode, c1["Q"], 10, 200, rerank=rr, visited_cap=4096)
+        finally:
+            ann.ann_set_launch(c1["ix"], mode, 0, 0, 0)
+        assert_same(got, ref, visited=True)
+    # 768-d inner product
+    ref = oracle.hnsw_search(v768["g"], store_for(v768, "bf16", "ip"), 10, 300, Q=v768["Q"],
+                             rerank_f32=v768["X"], rerank=40)
+    ann.ann_set_launch(v768["ix"], "bf16", waves_per_query=waves)
+    try:
+        got = gpu(v768["ix"], "bf16", v768["Q"], 10, 300, rerank=40)
+    finally:
+        ann.ann_set_launch(v768["ix"], "bf16", 0, 0, 0)
+    assert_same(got, ref)
+    # sparse
+    s = sparse_small
+    ix = ann.ann_index_create(s["graph"], "ip", s["vocab"], sp_indptr=s["indptr"], sp_ids=s["ids"],
+                              sp_vals=s["vals"])
+    try:
+        qp, qi, qv = s["q"]
+        sq = (torch.from_numpy(qp).to(DEV), torch.from_numpy(qi.view(np.int16)).to(DEV),
+              torch.from_numpy(qv).to(DEV))
+        ann.ann_set_launch(ix, "sparse", waves_per_query=waves)
+        r = ann.ann_search_ex(ix, "sparse", sparse=sq, k=10, ef=100, want_stats=True)
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in r.items()}
+        assert_same(got, oracle.hnsw_search(s["graph"], s["store"], 10, 100, sparse_q=s["q"]))
+    finally:
+        ix.close()
+
+
+def test_pq_with_waves(c1):
+    X = c1["X"]
+    sample, init = synth.pq_sample(0, X.shape[0], 5000, 256)
+    cb, _, _ = oracle.pq_train(X, 16, 256, sample, init, max_iter=4)
+    codes = oracle.pq_encode(X, cb)
+    ix = ann.ann_index_create(c1["g"], "l2", X.shape[1], x_f32=X, pq_codebook=cb, pq_codes=codes)
+    try:
+        ref = oracle.hnsw_search(c1["g"], oracle.pq_store(cb, codes, "l2"), 10, 100, Q=c1["Q"],
+                                 rerank_f32=X, rerank=30)
+        for waves in (2, 4):
+            say("pq waves", waves)
+            ann.ann_set_launch(ix, "pq", waves_per_query=waves)
+            assert_same(gpu(ix, "pq", c1["Q"], 10, 100, rerank=30), ref)
+    finally:
+        ix.close()
