@@ -229,9 +229,10 @@ int ann_search_sparse(const ann_index* ix, const int64_t* q_indptr, const uint16
 /*
  * The traversal kernel is persistent: `slots` workgroups pull query indices
  * from a device counter, one query per workgroup at a time.  A workgroup has
- * waves_per_query wavefronts (1, 2 or 4): they share the query's beam in LDS
- * and split the row gathers of each expansion, so a large beam (whose LDS
- * limits the queries per compute unit) still keeps many rows in flight.
+ * waves_per_query wavefronts (1, 2, 4 or 8): they share the query's beam in
+ * LDS, split the row gathers of each expansion and merge new entries into the
+ * beam together, so a large beam (whose LDS limits the queries per compute
+ * unit) still keeps many rows in flight.
  * lanes_per_row (16, 32 or 64) is how many lanes evaluate one dense row
  * together.  Zeros select the built-in defaults (or the autotuned values,
  * once ann_autotune has run).  Results do not depend on these settings.

@@ -265,7 +265,7 @@ int default_waves(const ann_index* ix, const SearchParams& P) {
     return 1;
   (void)ix;
   const int ratio = without / with_lds;
-  return ratio >= 4 ? 4 : ratio >= 2 ? 2 : 1;
+  return ratio >= 8 ? 8 : ratio >= 4 ? 4 : ratio >= 2 ? 2 : 1;
 }
 
 int64_t pick_slots(const ann_index* ix, const SearchParams& P, int64_t requested) {
@@ -494,8 +494,8 @@ int ann_set_launch(ann_index* ix, int32_t mode, const ann_launch_cfg* cfg) {
   if (mode < 0 || mode > ANN_MODE_SPARSE) return fail(ANN_EINVAL, "unknown mode");
   if (cfg->slots < 0) return fail(ANN_EINVAL, "slots < 0");
   if (cfg->waves_per_query != 0 && cfg->waves_per_query != 1 && cfg->waves_per_query != 2 &&
-      cfg->waves_per_query != 4)
-    return fail(ANN_EINVAL, "waves_per_query must be 0, 1, 2 or 4");
+      cfg->waves_per_query != 4 && cfg->waves_per_query != 8)
+    return fail(ANN_EINVAL, "waves_per_query must be 0, 1, 2, 4 or 8");
   if (cfg->lanes_per_row != 0) {
     if (!is_dense(mode)) return fail(ANN_EINVAL, "lanes_per_row applies to dense modes");
     if (!dense_shape_supported(mode, ix->d * elem_bytes(mode) / 16, cfg->lanes_per_row))
@@ -524,7 +524,7 @@ int ann_autotune(ann_index* ix, const ann_batch* b, ann_launch_cfg* best) {
   std::vector<int> lanes = is_dense(b->mode) ? std::vector<int>{16, 32, 64} : std::vector<int>{0};
   for (int L : lanes) {
     if (L && !dense_shape_supported(b->mode, P.nchunks, L)) continue;
-    for (int nw : {1, 2, 4})
+    for (int nw : {1, 2, 4, 8})
       for (int mult : {1, 2, 4, 8, 16}) cands.push_back(ann_launch_cfg{ix->cu_count * mult, L, nw});
   }
   std::lock_guard<std::mutex> lock(ix->mu);

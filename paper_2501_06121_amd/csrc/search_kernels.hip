@@ -479,25 +479,19 @@ __device__ __forceinline__ int rank_in_w(const Lds& s, int w, float k, uint32_t 
   return lo;
 }
 
-// Merge the sorted new entries held by lanes 0..mnew-1 into W (size w,
-// capacity ef).  Returns the new size; *first_pos = where the best new entry
-// landed (or a large value if none).
-__device__ int merge_into_w(const Lds& s, int w, int ef, int mnew, float k, uint32_t id,
-                            int* first_pos) {
-  const int lane = lane_id();
-  int r = 0;
-  if (lane < mnew) {
-    r = rank_in_w(s, w, k, id);
-    s.rnk[lane] = r;
-  }
-  wave_sync();
-  const int r0 = uniform_int(__shfl(r, 0, 64));
-  // shift the tail [r0, w) up by the number of new entries ranked at or below
-  // each position; highest chunk first so no unread entry is overwritten
+// Merge the sorted new entries s.ckey/s.cid[0, mnew) whose ranks in W are
+// s.rnk[0, mnew) into W (size w, capacity ef); every thread of the workgroup
+// takes part.  The tail [r0, w) moves up by the number of new entries ranked
+// at or below each position; chunks go from the highest down, each read
+// completely before it is written, so no unread entry is overwritten.
+// Returns the new size.
+__device__ int merge_into_w(const Lds& s, int w, int ef, int mnew, int r0) {
+  const int tid = threadIdx.x;
+  const int nthr = blockDim.x;
   if (w > r0) {
-    const int top = r0 + ((w - 1 - r0) & ~63);
-    for (int j0 = top; j0 >= r0; j0 -= 64) {
-      const int j = j0 + lane;
+    const int top = r0 + ((w - 1 - r0) / nthr) * nthr;
+    for (int j0 = top; j0 >= r0; j0 -= nthr) {
+      const int j = j0 + tid;
       float wk = 0.0f;
       uint32_t wi = 0u;
       int dest = ef;
@@ -506,7 +500,7 @@ __device__ int merge_into_w(const Lds& s, int w, int ef, int mnew, float k, uint
         wi = s.wid[j];
         int cnt = 0;                  // new entries ranked at or below j
         if (mnew <= 16) {
-          for (int i = 0; i < mnew; ++i) cnt += (__builtin_amdgcn_readlane(r, i) <= j) ? 1 : 0;
+          for (int i = 0; i < mnew; ++i) cnt += (s.rnk[i] <= j) ? 1 : 0;
         } else {
           int lo = 0, hi = mnew;
           while (lo < hi) {
@@ -517,17 +511,16 @@ __device__ int merge_into_w(const Lds& s, int w, int ef, int mnew, float k, uint
         }
         dest = j + cnt;
       }
-      wave_sync();
+      __syncthreads();
       if (j < w && dest < ef) { s.wkey[dest] = wk; s.wid[dest] = wi; }
-      wave_sync();
+      __syncthreads();
     }
   }
-  if (lane < mnew) {
-    const int pos = r + lane;
-    if (pos < ef) { s.wkey[pos] = k; s.wid[pos] = id; }
+  if (tid < mnew) {
+    const int pos = s.rnk[tid] + tid;
+    if (pos < ef) { s.wkey[pos] = s.ckey[tid]; s.wid[pos] = (uint32_t)s.cid[tid]; }
   }
-  wave_sync();
-  *first_pos = (mnew > 0) ? r0 : 0x7FFFFFFF;
+  __syncthreads();
   const int nw = w + mnew;
   return nw < ef ? nw : ef;
 }
@@ -694,15 +687,22 @@ __device__ void run_query(const SearchParams& p, const Lds& s, Policy& pol, int 
           if (lane >= mnew) { kk = __builtin_inff(); ki = kIdMask; }
           sort_lanes(kk, ki, sz);
         }
-        int first_pos;
-        w = merge_into_w(s, w, ef, mnew, kk, ki, &first_pos);
-        if (first_pos < hint) hint = first_pos;
+        // ranks in W of the sorted new entries, published with the entries
+        if (lane < mnew) {
+          s.rnk[lane] = rank_in_w(s, w, kk, ki);
+          s.ckey[lane] = kk;
+          s.cid[lane] = (int32_t)ki;
+        }
       }
-      if (lane == 0) { s.ctl[CTL_W] = w; s.ctl[CTL_HINT] = hint; }
+      if (lane == 0) s.ctl[CTL_M] = mnew;
     }
     __syncthreads();
-    w = s.ctl[CTL_W];
-    hint = s.ctl[CTL_HINT];
+    const int mnew = s.ctl[CTL_M];
+    if (mnew > 0) {
+      const int r0 = s.rnk[0];
+      w = merge_into_w(s, w, ef, mnew, r0);
+      if (r0 < hint) hint = r0;
+    }
   }
   if (wave == 0 && lane == 0) {
     s.ctl[CTL_VISITED] = st.visited;
@@ -814,7 +814,7 @@ __device__ void run_query(const SearchParams& p, const Lds& s, Policy& pol, int 
 }
 
 template <class Policy>
-__global__ void __launch_bounds__(256) search_kernel(SearchParams p) {
+__global__ void __launch_bounds__(512) search_kernel(SearchParams p) {
   extern __shared__ __align__(16) char lds_raw[];
   const Lds s = carve(lds_raw, p);
   Policy pol;

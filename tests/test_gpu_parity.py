@@ -225,7 +225,7 @@ def test_ann_search_blocking_api(c1):
     assert np.array_equal(d.cpu().numpy(), ref["keys"])
 
 
-@pytest.mark.parametrize("waves", [2, 4])
+@pytest.mark.parametrize("waves", [2, 4, 8])
 def test_waves_per_query_do_not_change_results(c1, v768, sparse_small, waves):
     say("waves per query", waves)
     # dense L2, with and without rerank
@@ -274,7 +274,7 @@ def test_pq_with_waves(c1):
     try:
         ref = oracle.hnsw_search(c1["g"], oracle.pq_store(cb, codes, "l2"), 10, 100, Q=c1["Q"],
                                  rerank_f32=X, rerank=30)
-        for waves in (2, 4):
+        for waves in (2, 4, 8):
             say("pq waves", waves)
             ann.ann_set_launch(ix, "pq", waves_per_query=waves)
             assert_same(gpu(ix, "pq", c1["Q"], 10, 100, rerank=30), ref)
