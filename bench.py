@@ -50,14 +50,7 @@ def load_workload(name, nq=None):
     gpath = os.path.join(ddir, "graph.npz")
     if not os.path.exists(gpath):
         raise SystemExit(f"missing {gpath}: build it with `python -m oracle.build_index {name}`")
-    z = np.load(gpath)
-    n, M, M0, L, e = (int(v) for v in z["meta"])
-
-    class G:
-        pass
-    g = G()
-    g.n, g.M, g.M0, g.max_level, g.entry = n, M, M0, L, e
-    g.levels, g.adj0, g.upper_off, g.upper_adj = z["levels"], z["adj0"], z["upper_off"], z["upper_adj"]
+    g = read_graph(gpath)
     t = time.time()
     X = synth.dense_base(spec)
     Q = synth.dense_queries(spec)
@@ -69,6 +62,27 @@ def load_workload(name, nq=None):
     if os.path.exists(gtp):
         gt = np.load(gtp)["ids"][:Q.shape[0]]
     return spec, g, X, Q, gt
+
+
+def read_graph(path):
+    """The graph file: meta (n, M, M0, max_level, entry), levels u8[n], layer-0
+    degrees u8[n] and ids packed in 3 little-endian bytes (lists back to back),
+    upper_off i32[n], upper_adj i32[lists][M].  Returns the layout the library
+    takes (layer-0 lists padded with -1 to M0)."""
+    z = np.load(path)
+    n, M, M0, L, e = (int(v) for v in z["meta"])
+
+    class G:
+        pass
+    g = G()
+    g.n, g.M, g.M0, g.max_level, g.entry = n, M, M0, L, e
+    g.levels, g.upper_off, g.upper_adj = z["levels"], z["upper_off"], z["upper_adj"]
+    deg = z["deg0"].astype(np.int64)
+    b = z["ids0"].reshape(-1, 3).astype(np.int32)
+    adj = np.full((n, M0), -1, np.int32)
+    adj[np.arange(M0)[None, :] < deg[:, None]] = b[:, 0] | (b[:, 1] << 8) | (b[:, 2] << 16)
+    g.adj0 = adj
+    return g
 
 
 def recall(ids, gt, k=10):

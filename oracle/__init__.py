@@ -286,15 +286,29 @@ class Graph:
         return row[row >= 0]
 
     def save(self, path):
+        """Compact file: layer-0 lists as degrees (u8) + ids packed in 3 bytes
+        (little endian; n < 2^24) without padding; upper lists as stored."""
+        assert self.n < (1 << 24)
+        deg = (self.adj0 >= 0).sum(1).astype(np.uint8)
+        ids = self.adj0[self.adj0 >= 0].astype(np.uint32)      # row-major: valid first in each row
+        packed = np.stack([(ids >> (8 * b)) & 0xFF for b in range(3)], axis=1).astype(np.uint8)
         np.savez(path, meta=np.array([self.n, self.M, self.M0, self.max_level, self.entry], np.int64),
-                 levels=self.levels, adj0=self.adj0, upper_off=self.upper_off,
+                 levels=self.levels, deg0=deg, ids0=packed.reshape(-1), upper_off=self.upper_off,
                  upper_adj=self.upper_adj)
 
     @classmethod
     def load(cls, path):
         z = np.load(path)
         n, M, M0, L, e = (int(v) for v in z["meta"])
-        return cls(n, M, M0, L, e, z["levels"], z["adj0"], z["upper_off"], z["upper_adj"])
+        if "adj0" in z:
+            adj0 = z["adj0"]
+        else:
+            deg = z["deg0"].astype(np.int64)
+            b = z["ids0"].reshape(-1, 3).astype(np.int32)
+            ids = b[:, 0] | (b[:, 1] << 8) | (b[:, 2] << 16)
+            adj0 = np.full((n, M0), -1, np.int32)
+            adj0[np.arange(M0)[None, :] < deg[:, None]] = ids
+        return cls(n, M, M0, L, e, z["levels"], adj0, z["upper_off"], z["upper_adj"])
 
 
 def hnsw_build(X, metric, M, efc, u_levels, seq_prefix=None, batch_frac=0.0, batch_cap=4096,
