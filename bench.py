@@ -193,6 +193,8 @@ def cpu_baseline(g, X, Q, mode, ef, k, rerank, budget_s=15.0):
     """The oracle's search (same mode, ef, rerank) on a sample of queries,
     all host cores (OpenMP across queries)."""
     import oracle
+    g = oracle.Graph(g.n, g.M, g.M0, g.max_level, g.entry, g.levels, g.adj0, g.upper_off,
+                     g.upper_adj)
     threads = os.cpu_count() or 1
     if mode == "f16":
         st = oracle.dense_store(X.astype(np.float16).view(np.uint16), "ip", "f16")
