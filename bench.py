@@ -379,9 +379,14 @@ def main():
 
 
 def kernel_sha():
+    """Hash of the search kernels' sources (the traffic counters describe one version)."""
+    import glob
     import hashlib
-    p = os.path.join(ROOT, "paper_2501_06121_amd", "csrc", "search_kernels.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2501_06121_amd", "csrc")
+    for p in sorted(glob.glob(os.path.join(csrc, "search_*"))):
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
 
 
 if __name__ == "__main__":

@@ -73,12 +73,13 @@ enum ann_mode {
   ANN_MODE_SPARSE = 5  /* sparse rows (CSR), inner product */
 };
 
-/* Largest ef (after ef_eff = max(ef, k)) one search can use: the beam lives
- * in on-chip memory (8 bytes per entry; 16384 entries take 128 KB of the
- * 160 KB LDS of a compute unit, leaving one query per unit).  Larger requests
- * fail with ANN_EBUDGET, as do requests whose on-chip footprint (beam, rerank
- * keys, PQ table) exceeds the LDS. */
-#define ANN_EF_MAX 16384
+/* Largest ef (after ef_eff = max(ef, k)) one search can use.  A beam costs 8
+ * bytes per entry: in on-chip memory (LDS, 160 KB per compute unit) up to
+ * about 20,000 entries fit, wider beams keep their sorted list in device
+ * memory (see ann_launch_cfg.beam_list).  Larger requests fail with
+ * ANN_EBUDGET, as do requests whose on-chip footprint (beam list when in LDS,
+ * insert buffer, rerank keys, PQ table) exceeds the LDS. */
+#define ANN_EF_MAX 65536
 /* Largest k and largest rerank depth. */
 #define ANN_K_MAX 1024
 
@@ -234,13 +235,31 @@ int ann_search_sparse(const ann_index* ix, const int64_t* q_indptr, const uint16
  * beam together, so a large beam (whose LDS limits the queries per compute
  * unit) still keeps many rows in flight.
  * lanes_per_row (16, 32 or 64) is how many lanes evaluate one dense row
- * together.  Zeros select the built-in defaults (or the autotuned values,
- * once ann_autotune has run).  Results do not depend on these settings.
+ * together.  beam_buffer is the capacity of the sorted insert buffer that a
+ * large beam uses in front of its sorted list (new entries are merged into
+ * the buffer, the buffer into the list only when it fills): 0 lets the
+ * library decide (queries with ef above 1024 use one sized from ef and the
+ * free LDS), -1 turns it off, and a value in [64, 4096] makes every query use
+ * a buffer of that size.  Zeros select the built-in defaults (or the
+ * autotuned values, once ann_autotune has run).  Results do not depend on
+ * these settings.
+ * beam_list says where the beam's sorted list lives: ANN_BEAM_LDS (on chip,
+ * which bounds ef by the LDS size and the queries per compute unit by the
+ * beam's footprint), ANN_BEAM_HBM (a per-slot array in device memory; only
+ * the insert buffer stays in LDS, so wide beams keep several queries per
+ * compute unit and ef may reach ANN_EF_MAX), or ANN_BEAM_AUTO (HBM for ef
+ * above 4096 or when the list does not fit in LDS).
  */
+#define ANN_BEAM_AUTO 0
+#define ANN_BEAM_LDS 1
+#define ANN_BEAM_HBM 2
+
 typedef struct ann_launch_cfg {
   int32_t slots;
   int32_t lanes_per_row;
   int32_t waves_per_query;
+  int32_t beam_buffer;
+  int32_t beam_list;
 } ann_launch_cfg;
 
 int ann_set_launch(ann_index* ix, int32_t mode, const ann_launch_cfg* cfg);

@@ -25,7 +25,8 @@ ERR_NAMES = {0: "ANN_OK", 1: "ANN_EINVAL", 2: "ANN_ENODEV", 3: "ANN_ENOMEM", 4: 
              5: "ANN_EFORMAT", 6: "ANN_EHIP", 7: "ANN_EUNSUP", 8: "ANN_EAGAIN"}
 METRIC = {"l2": 0, "ip": 1}
 MODE = {"f32": 0, "f16": 1, "bf16": 2, "fp8": 3, "pq": 4, "sparse": 5}
-ANN_EF_MAX = 16384
+ANN_EF_MAX = 65536
+ANN_BEAM_AUTO, ANN_BEAM_LDS, ANN_BEAM_HBM = 0, 1, 2
 ANN_K_MAX = 1024
 
 P = C.c_void_p
@@ -56,7 +57,8 @@ class AnnBatch(C.Structure):
 
 
 class AnnLaunchCfg(C.Structure):
-    _fields_ = [("slots", I32), ("lanes_per_row", I32), ("waves_per_query", I32)]
+    _fields_ = [("slots", I32), ("lanes_per_row", I32), ("waves_per_query", I32),
+                ("beam_buffer", I32), ("beam_list", I32)]
 
 
 class AnnServerCfg(C.Structure):
@@ -307,8 +309,13 @@ def ann_search_sparse(index, indptr, ids, vals, k, ef):
     return out_ids, out_d
 
 
-def ann_set_launch(index, mode, slots=0, lanes_per_row=0, waves_per_query=0):
-    cfg = AnnLaunchCfg(int(slots), int(lanes_per_row), int(waves_per_query))
+BEAM_LIST = {"auto": ANN_BEAM_AUTO, "lds": ANN_BEAM_LDS, "hbm": ANN_BEAM_HBM}
+
+
+def ann_set_launch(index, mode, slots=0, lanes_per_row=0, waves_per_query=0, beam_buffer=0,
+                   beam_list="auto"):
+    bl = BEAM_LIST[beam_list] if isinstance(beam_list, str) else int(beam_list)
+    cfg = AnnLaunchCfg(int(slots), int(lanes_per_row), int(waves_per_query), int(beam_buffer), bl)
     _check(lib().ann_set_launch(index.handle, MODE[mode] if isinstance(mode, str) else int(mode),
                                 C.byref(cfg)))
 
@@ -318,7 +325,8 @@ def ann_get_launch(index, mode):
     _check(lib().ann_get_launch(index.handle, MODE[mode] if isinstance(mode, str) else int(mode),
                                 C.byref(cfg)))
     return {"slots": cfg.slots, "lanes_per_row": cfg.lanes_per_row,
-            "waves_per_query": cfg.waves_per_query}
+            "waves_per_query": cfg.waves_per_query, "beam_buffer": cfg.beam_buffer,
+            "beam_list": cfg.beam_list}
 
 
 def ann_autotune(index, mode="f32", queries=None, sparse=None, k=10, ef=64, rerank=0):
@@ -339,7 +347,8 @@ def ann_autotune(index, mode="f32", queries=None, sparse=None, k=10, ef=64, rera
     cfg = AnnLaunchCfg()
     _check(lib().ann_autotune(index.handle, C.byref(b), C.byref(cfg)))
     return {"slots": cfg.slots, "lanes_per_row": cfg.lanes_per_row,
-            "waves_per_query": cfg.waves_per_query}
+            "waves_per_query": cfg.waves_per_query, "beam_buffer": cfg.beam_buffer,
+            "beam_list": cfg.beam_list}
 
 
 def ann_bruteforce(index, queries, k, stream=None):

@@ -47,9 +47,13 @@ void Workspace::release() {
   if (bits) (void)hipFree(bits);
   if (vlog) (void)hipFree(vlog);
   if (counter) (void)hipFree(counter);
+  if (beam_key) (void)hipFree(beam_key);
+  if (beam_id) (void)hipFree(beam_id);
   if (done) (void)hipEventDestroy(done);
   bits = nullptr; vlog = nullptr; counter = nullptr; done = nullptr;
+  beam_key = nullptr; beam_id = nullptr;
   slots = 0;
+  beam_cap = 0;
   bytes = 0;
 }
 
@@ -60,6 +64,11 @@ int64_t slot_bytes(int64_t n) {
 }  // namespace ann
 
 namespace {
+
+// Beams wider than this get an insert buffer when the launch leaves it to the
+// library, and beams wider than kHbmListMinEf keep their list in HBM.
+constexpr int kBufferMinEf = 1024;
+constexpr int kHbmListMinEf = 4096;
 
 template <class T>
 int upload(T** dst, const T* src, size_t count, int64_t* bytes) {
@@ -147,9 +156,11 @@ namespace ann {
 
 int default_waves(const ann_index* ix, const SearchParams& P);
 
-int ensure_workspace(ann_index* ix, Workspace& ws, int64_t slots) {
-  if (ws.slots >= slots && ws.device == ix->device) return ANN_OK;
+int ensure_workspace(ann_index* ix, Workspace& ws, int64_t slots, int64_t beam_cap) {
+  if (ws.slots >= slots && ws.beam_cap >= beam_cap && ws.device == ix->device) return ANN_OK;
   if (ws.done) HIP_OR_RETURN(hipEventSynchronize(ws.done), "hipEventSynchronize");
+  slots = std::max(slots, ws.slots);
+  beam_cap = std::max(beam_cap, ws.beam_cap);
   ws.release();
   ws.device = ix->device;
   ws.bits_words = (ix->n + 31) / 32;
@@ -159,10 +170,25 @@ int ensure_workspace(ann_index* ix, Workspace& ws, int64_t slots) {
   HIP_OR_RETURN(hipMalloc((void**)&ws.vlog, (size_t)slots * ws.vlog_cap * 4), "hipMalloc (visited log)");
   HIP_OR_RETURN(hipMalloc((void**)&ws.counter, 64), "hipMalloc (counter)");
   HIP_OR_RETURN(hipEventCreateWithFlags(&ws.done, hipEventDisableTiming), "hipEventCreate");
+  if (beam_cap > 0) {
+    HIP_OR_RETURN(hipMalloc((void**)&ws.beam_key, (size_t)slots * beam_cap * 4), "hipMalloc (beam keys)");
+    HIP_OR_RETURN(hipMalloc((void**)&ws.beam_id, (size_t)slots * beam_cap * 4), "hipMalloc (beam ids)");
+  }
   ws.slots = slots;
+  ws.beam_cap = beam_cap;
   ws.used = false;
-  ws.bytes = slots * ws.bits_words * 4 + slots * (int64_t)ws.vlog_cap * 4 + 64;
+  ws.bytes = slots * ws.bits_words * 4 + slots * (int64_t)ws.vlog_cap * 4 + 64 + slots * beam_cap * 8;
   return ANN_OK;
+}
+
+void bind_workspace(SearchParams& P, const Workspace& ws) {
+  P.bits = ws.bits;
+  P.bits_words = ws.bits_words;
+  P.vlog = ws.vlog;
+  P.vlog_cap = ws.vlog_cap;
+  P.counter = ws.counter;
+  P.glist_key = ws.beam_key;
+  P.glist_id = ws.beam_id;
 }
 
 // Fills the kernel parameters for a batch; checks everything on the host.
@@ -246,6 +272,29 @@ int make_params(const ann_index* ix, const ann_batch* b, SearchParams* P) {
   P->out_stats = b->out_stats;
   P->out_visited = b->out_visited;
   P->visited_cap = b->visited_cap;
+  // where the beam lives: its list in LDS, or (wide beams) in HBM with only
+  // the insert buffer in LDS
+  P->glist = cfg.beam_list == ANN_BEAM_HBM ||
+             (cfg.beam_list == ANN_BEAM_AUTO && (ef_cap > kHbmListMinEf || lds_bytes(*P) > ix->lds_limit));
+  if (P->glist) {
+    if (cfg.beam_buffer == -1)
+      return fail(ANN_EINVAL, "a beam list in HBM needs the insert buffer (beam_buffer is -1)");
+    P->wbuf = cfg.beam_buffer > 0 ? cfg.beam_buffer : 1024;
+    P->wbuf_min_ef = 0;
+  } else if (cfg.beam_buffer > 0) {
+    P->wbuf = cfg.beam_buffer;
+    P->wbuf_min_ef = 0;
+  } else if (cfg.beam_buffer == 0 && ef_cap > kBufferMinEf) {
+    // an eighth of the beam, 128..1024 entries, halved until it fits
+    int wb = 128;
+    while (wb < 1024 && wb < ef_cap / 8) wb <<= 1;
+    P->wbuf_min_ef = kBufferMinEf;
+    for (; wb >= 64; wb >>= 1) {
+      P->wbuf = wb;
+      if (lds_bytes(*P) <= ix->lds_limit) break;
+    }
+    if (wb < 64) P->wbuf = 0;
+  }
   if (lds_bytes(*P) > ix->lds_limit)
     return fail(ANN_EBUDGET, "on-chip memory for ef %d in mode %d: %zu bytes > %zu", ef_cap, mode,
                 lds_bytes(*P), ix->lds_limit);
@@ -257,6 +306,9 @@ int make_params(const ann_index* ix, const ann_batch* b, SearchParams* P) {
 // many queries a compute unit holds: the spare wave slots then gather rows
 // for the resident queries.
 int default_waves(const ann_index* ix, const SearchParams& P) {
+  // a beam list in HBM leaves the LDS nearly free: many queries per compute
+  // unit, two waves each (measured best for wide beams)
+  if (P.glist) return 2;
   const void* fn = kernel_symbol(P);
   if (!fn) return 1;
   int with_lds = 0, without = 0;
@@ -277,8 +329,8 @@ int64_t pick_slots(const ann_index* ix, const SearchParams& P, int64_t requested
     per_cu = 0;
   if (per_cu <= 0) per_cu = 4;
   int64_t slots = requested > 0 ? requested : (int64_t)ix->cu_count * per_cu;
-  // bound the visited bitsets to 4 GiB
-  const int64_t per_slot = slot_bytes(ix->n);
+  // bound the visited bitsets (and HBM beam lists) to 4 GiB
+  const int64_t per_slot = slot_bytes(ix->n) + (P.glist ? (int64_t)P.ef_cap * 8 : 0);
   slots = std::min<int64_t>(slots, std::max<int64_t>(1, (int64_t(4) << 30) / per_slot));
   slots = std::min<int64_t>(slots, std::max<int64_t>(1, P.nq));
   return std::max<int64_t>(1, slots);
@@ -290,14 +342,10 @@ int run_batch(ann_index* ix, Workspace& ws, const SearchParams& P0, int64_t slot
   HIP_OR_RETURN(hipSetDevice(ix->device), "hipSetDevice");
   SearchParams P = P0;
   const int64_t slots = pick_slots(ix, P, slots_req);
-  int rc = ensure_workspace(ix, ws, slots);
+  int rc = ensure_workspace(ix, ws, slots, P.glist ? P.ef_cap : 0);
   if (rc) return rc;
   if (ws.used) HIP_OR_RETURN(hipStreamWaitEvent(st, ws.done, 0), "hipStreamWaitEvent");
-  P.bits = ws.bits;
-  P.bits_words = ws.bits_words;
-  P.vlog = ws.vlog;
-  P.vlog_cap = ws.vlog_cap;
-  P.counter = ws.counter;
+  bind_workspace(P, ws);
   const size_t lds = lds_bytes(P);
   if (lds > 65536) {
     const void* fn = kernel_symbol(P);
@@ -496,6 +544,11 @@ int ann_set_launch(ann_index* ix, int32_t mode, const ann_launch_cfg* cfg) {
   if (cfg->waves_per_query != 0 && cfg->waves_per_query != 1 && cfg->waves_per_query != 2 &&
       cfg->waves_per_query != 4 && cfg->waves_per_query != 8)
     return fail(ANN_EINVAL, "waves_per_query must be 0, 1, 2, 4 or 8");
+  if (cfg->beam_buffer != 0 && cfg->beam_buffer != -1 &&
+      (cfg->beam_buffer < 64 || cfg->beam_buffer > 4096))
+    return fail(ANN_EINVAL, "beam_buffer must be 0, -1 or in [64, 4096]");
+  if (cfg->beam_list != ANN_BEAM_AUTO && cfg->beam_list != ANN_BEAM_LDS && cfg->beam_list != ANN_BEAM_HBM)
+    return fail(ANN_EINVAL, "beam_list must be ANN_BEAM_AUTO, ANN_BEAM_LDS or ANN_BEAM_HBM");
   if (cfg->lanes_per_row != 0) {
     if (!is_dense(mode)) return fail(ANN_EINVAL, "lanes_per_row applies to dense modes");
     if (!dense_shape_supported(mode, ix->d * elem_bytes(mode) / 16, cfg->lanes_per_row))
@@ -525,7 +578,8 @@ int ann_autotune(ann_index* ix, const ann_batch* b, ann_launch_cfg* best) {
   for (int L : lanes) {
     if (L && !dense_shape_supported(b->mode, P.nchunks, L)) continue;
     for (int nw : {1, 2, 4, 8})
-      for (int mult : {1, 2, 4, 8, 16}) cands.push_back(ann_launch_cfg{ix->cu_count * mult, L, nw});
+      for (int mult : {1, 2, 4, 8, 16}) cands.push_back(ann_launch_cfg{ix->cu_count * mult, L, nw, ix->cfg[b->mode].beam_buffer,
+                                        ix->cfg[b->mode].beam_list});
   }
   std::lock_guard<std::mutex> lock(ix->mu);
   hipEvent_t e0, e1;

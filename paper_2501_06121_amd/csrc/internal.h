@@ -31,6 +31,9 @@ struct Workspace {
   uint32_t* bits = nullptr;
   int32_t* vlog = nullptr;
   int32_t* counter = nullptr;
+  int64_t beam_cap = 0;              // beam-list entries per slot held in HBM
+  float* beam_key = nullptr;
+  uint32_t* beam_id = nullptr;
   hipEvent_t done = nullptr;
   bool used = false;
   int64_t bytes = 0;
@@ -79,8 +82,11 @@ namespace ann {
 
 // Kernel parameters for a batch; every argument is checked on the host.
 int make_params(const ann_index* ix, const ann_batch* b, SearchParams* P);
-// Allocates (or grows) a workspace for `slots` slots.
-int ensure_workspace(ann_index* ix, Workspace& ws, int64_t slots);
+// Allocates (or grows) a workspace for `slots` slots, with room for beam
+// lists of `beam_cap` entries per slot in HBM (0: none).
+int ensure_workspace(ann_index* ix, Workspace& ws, int64_t slots, int64_t beam_cap);
+// Points the kernel parameters at a workspace's arrays.
+void bind_workspace(SearchParams& P, const Workspace& ws);
 // Launches one batch with workspace `ws` on stream `st` (asynchronous).
 // slots_req = 0 picks the default (occupancy x CUs, bounded by memory).
 int run_batch(ann_index* ix, Workspace& ws, const SearchParams& P, int64_t slots_req,

@@ -41,6 +41,11 @@ struct SearchParams {
   const int32_t* ef_arr;
   int k_all, ef_all, k_max, ef_cap, rerank;
   int q_lds_floats;
+  int wbuf;                         // insert-buffer entries of a large beam (0: none)
+  int wbuf_min_ef;                  // queries with ef above this use the buffer
+  int glist;                        // beam list in HBM (glist_key/glist_id) instead of LDS
+  float* glist_key;                 // [slots][ef_cap]
+  uint32_t* glist_id;               // [slots][ef_cap]
   int64_t* out_ids;
   float* out_dists;
   int32_t* out_status;
@@ -55,10 +60,28 @@ struct SearchParams {
   int32_t* counter;
 };
 
+// Entries of the sparse query's hash table in LDS (at most half filled).
+constexpr int kSparseHashSlots = 512;
+
+// Rerank keys held at once: R_eff <= min(max(R, k_max), ef_cap).
+__host__ __device__ inline int rerank_slots(const SearchParams& p) {
+  if (p.rerank <= 0) return 0;
+  const int r = p.rerank > p.k_max ? p.rerank : p.k_max;
+  return r < p.ef_cap ? r : p.ef_cap;
+}
+
 hipError_t launch_search(const SearchParams& p, int slots, size_t lds, hipStream_t st);
 size_t lds_bytes(const SearchParams& p);
 const void* kernel_symbol(const SearchParams& p);
 bool dense_shape_supported(int mode, int nchunks, int lanes_per_row);
+
+// kernel of a batch, one function per storage mode (search_<mode>.hip)
+const void* symbol_f32(const SearchParams& p);
+const void* symbol_f16(const SearchParams& p);
+const void* symbol_bf16(const SearchParams& p);
+const void* symbol_fp8(const SearchParams& p);
+const void* symbol_pq(const SearchParams& p);
+const void* symbol_sparse(const SearchParams& p);
 
 // brute force on matrix cores
 hipError_t launch_bruteforce(const float* X, int64_t n, int d, int metric, const float* Q,

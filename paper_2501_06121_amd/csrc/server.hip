@@ -141,11 +141,7 @@ int ann_server::capture(Lane& L) {
   P.out_ids = L.dids;
   P.out_dists = L.dd;
   P.out_status = L.dstat;
-  P.bits = L.ws.bits;
-  P.bits_words = L.ws.bits_words;
-  P.vlog = L.ws.vlog;
-  P.vlog_cap = L.ws.vlog_cap;
-  P.counter = L.ws.counter;
+  bind_workspace(P, L.ws);
   const size_t lds = lds_bytes(P);
   if (lds > 65536) {
     const void* fn = kernel_symbol(P);
@@ -281,8 +277,9 @@ int ann_server_create(const ann_index* cix, const ann_server_cfg* cfg, ann_serve
   const int64_t batch_bytes = max_batch * ((int64_t)ix->d * 4 + 8 + (int64_t)c.k_max * 12 + 4);
   P.nq = max_batch;
   int64_t slots = pick_slots(ix, P, 0);
-  while (slots > 1 && c.streams * (batch_bytes + slots * slot_bytes(ix->n)) > c.hbm_budget) slots /= 2;
-  if (c.streams * (batch_bytes + slots * slot_bytes(ix->n)) > c.hbm_budget)
+  const int64_t per_slot = slot_bytes(ix->n) + (proto.glist ? (int64_t)proto.ef_cap * 8 : 0);
+  while (slots > 1 && c.streams * (batch_bytes + slots * per_slot) > c.hbm_budget) slots /= 2;
+  if (c.streams * (batch_bytes + slots * per_slot) > c.hbm_budget)
     return fail(ANN_EBUDGET, "hbm_budget %lld too small for one slot per stream", (long long)c.hbm_budget);
   s->slots = slots;
   s->proto = proto;
@@ -291,7 +288,10 @@ int ann_server_create(const ann_index* cix, const ann_server_cfg* cfg, ann_serve
   for (Lane& L : s->lanes) {
     HIP_OR_RETURN(hipStreamCreateWithFlags(&L.st, hipStreamNonBlocking), "hipStreamCreate");
     HIP_OR_RETURN(hipEventCreateWithFlags(&L.ev, hipEventDisableTiming), "hipEventCreate");
-    if ((rc = ensure_workspace(ix, L.ws, slots))) { s->free_lanes(); return rc; }
+    if ((rc = ensure_workspace(ix, L.ws, slots, proto.glist ? proto.ef_cap : 0))) {
+      s->free_lanes();
+      return rc;
+    }
     const size_t nb = (size_t)max_batch;
     HIP_OR_RETURN(hipMalloc((void**)&L.dq, sizeof(float) * nb * ix->d), "hipMalloc");
     HIP_OR_RETURN(hipMalloc((void**)&L.dk, sizeof(int32_t) * nb), "hipMalloc");

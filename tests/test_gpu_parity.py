@@ -195,7 +195,7 @@ def test_edge_cases(c1):
     assert np.array_equal(a["ids"], b["ids"])
     # over-capacity requests fail on the host
     with pytest.raises(ann.AnnError) as e:
-        gpu(ix, "f32", c1["Q"][:2], 10, 20000)
+        gpu(ix, "f32", c1["Q"][:2], 10, ann.ANN_EF_MAX + 1)
     assert e.value.code == ann.ANN_EBUDGET
     # a 3-node graph: fewer nodes than k -> padding
     X = np.zeros((3, 16), np.float32); X[:, 0] = [0, 1, 5]
@@ -280,3 +280,96 @@ def test_pq_with_waves(c1):
             assert_same(gpu(ix, "pq", c1["Q"], 10, 100, rerank=30), ref)
     finally:
         ix.close()
+
+
+@pytest.mark.parametrize("buf,place", [(64, "lds"), (200, "lds"), (-1, "lds"), (0, "auto"),
+                                       (64, "hbm"), (0, "hbm")])
+def test_beam_layouts_do_not_change_results(c1, v768, sparse_small, buf, place):
+    """The insert buffer of a wide beam, and a beam list kept in HBM, hold the
+    same W as one sorted list in LDS: forced small buffers (many flushes,
+    cuts from both tails) at every beam width, the automatic choice (buffer
+    above ef 1024, HBM list above 4096), none, and the HBM list."""
+    say("beam layout", buf, place)
+    ann.ann_set_launch(c1["ix"], "f32", beam_buffer=buf, beam_list=place)
+    try:
+        for ef in (1, 10, 64, 700, 2000, 5000):
+            ref = oracle.hnsw_search(c1["g"], oracle.dense_store(c1["X"], "l2"), 10, ef, Q=c1["Q"],
+                                     visited_cap=10000)
+            assert_same(gpu(c1["ix"], "f32", c1["Q"], 10, ef, visited_cap=10000), ref, visited=True)
+        rng = np.random.default_rng(1)
+        nq = c1["Q"].shape[0]
+        k = rng.choice([1, 10, 100], nq).astype(np.int32)
+        ef = rng.choice([16, 100, 1500, 3000], nq).astype(np.int32)
+        ref = oracle.hnsw_search(c1["g"], oracle.dense_store(c1["X"], "l2"), k, ef, Q=c1["Q"])
+        assert_same(gpu(c1["ix"], "f32", c1["Q"], k, ef, k_max=100, ef_max=3000), ref)
+    finally:
+        ann.ann_set_launch(c1["ix"], "f32")
+    # 768-d inner product, FP16 rows and FP32 rerank, several waves
+    ann.ann_set_launch(v768["ix"], "f16", waves_per_query=4, beam_buffer=buf, beam_list=place)
+    try:
+        ref = oracle.hnsw_search(v768["g"], store_for(v768, "f16", "ip"), 10, 1200, Q=v768["Q"],
+                                 rerank_f32=v768["X"], rerank=40)
+        assert_same(gpu(v768["ix"], "f16", v768["Q"], 10, 1200, rerank=40), ref)
+    finally:
+        ann.ann_set_launch(v768["ix"], "f16")
+    # sparse rows
+    if buf > 0:
+        s = sparse_small
+        ix = ann.ann_index_create(s["graph"], "ip", s["vocab"], sp_indptr=s["indptr"],
+                                  sp_ids=s["ids"], sp_vals=s["vals"])
+        try:
+            qp, qi, qv = s["q"]
+            sq = (torch.from_numpy(qp).to(DEV), torch.from_numpy(qi.view(np.int16)).to(DEV),
+                  torch.from_numpy(qv).to(DEV))
+            ann.ann_set_launch(ix, "sparse", beam_buffer=buf, beam_list=place)
+            r = ann.ann_search_ex(ix, "sparse", sparse=sq, k=10, ef=300, want_stats=True)
+            torch.cuda.synchronize()
+            got = {k_: v.cpu().numpy() for k_, v in r.items()}
+            assert_same(got, oracle.hnsw_search(s["graph"], s["store"], 10, 300, sparse_q=s["q"]))
+        finally:
+            ix.close()
+
+
+def test_pq_with_hbm_beam(c1):
+    X = c1["X"]
+    sample, init = synth.pq_sample(0, X.shape[0], 5000, 256)
+    cb, _, _ = oracle.pq_train(X, 16, 256, sample, init, max_iter=4)
+    codes = oracle.pq_encode(X, cb)
+    ix = ann.ann_index_create(c1["g"], "l2", X.shape[1], x_f32=X, pq_codebook=cb, pq_codes=codes)
+    try:
+        ref = oracle.hnsw_search(c1["g"], oracle.pq_store(cb, codes, "l2"), 10, 1000, Q=c1["Q"],
+                                 rerank_f32=X, rerank=30)
+        ann.ann_set_launch(ix, "pq", waves_per_query=2, beam_list="hbm")
+        assert_same(gpu(ix, "pq", c1["Q"], 10, 1000, rerank=30), ref)
+    finally:
+        ix.close()
+
+
+def test_beam_buffer_bounds(c1):
+    for bad in (-2, 1, 63, 4097):
+        with pytest.raises(ann.AnnError) as e:
+            ann.ann_set_launch(c1["ix"], "f32", beam_buffer=bad)
+        assert e.value.code == ann.ANN_EINVAL
+    with pytest.raises(ann.AnnError) as e:
+        ann.ann_set_launch(c1["ix"], "f32", beam_list=3)
+    assert e.value.code == ann.ANN_EINVAL
+    assert ann.ann_get_launch(c1["ix"], "f32")["beam_buffer"] == 0
+    # an HBM list needs the insert buffer
+    ann.ann_set_launch(c1["ix"], "f32", beam_buffer=-1, beam_list="hbm")
+    try:
+        with pytest.raises(ann.AnnError) as e:
+            gpu(c1["ix"], "f32", c1["Q"][:2], 10, 100)
+        assert e.value.code == ann.ANN_EINVAL
+    finally:
+        ann.ann_set_launch(c1["ix"], "f32")
+    # a list forced into LDS stops at its size; ANN_EF_MAX bounds the HBM list
+    ann.ann_set_launch(c1["ix"], "f32", beam_list="lds")
+    try:
+        with pytest.raises(ann.AnnError) as e:
+            gpu(c1["ix"], "f32", c1["Q"][:2], 10, 21000)
+        assert e.value.code == ann.ANN_EBUDGET
+    finally:
+        ann.ann_set_launch(c1["ix"], "f32")
+    with pytest.raises(ann.AnnError) as e:
+        gpu(c1["ix"], "f32", c1["Q"][:2], 10, ann.ANN_EF_MAX + 1)
+    assert e.value.code == ann.ANN_EBUDGET
