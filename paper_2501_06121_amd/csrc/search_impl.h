@@ -40,7 +40,7 @@ namespace ann {
 
 // 16-byte chunks each lane keeps in flight while scoring rows (4 VGPRs each).
 #ifndef ANN_ROW_CHUNKS
-#define ANN_ROW_CHUNKS 8
+#define ANN_ROW_CHUNKS 16
 #endif
 
 constexpr uint32_t kExpanded = 0x80000000u;
@@ -124,7 +124,6 @@ struct Lds {
   int32_t* rnk;      // [64] insertion ranks
   float* bkey;       // [wbuf] insert buffer of a large beam
   uint32_t* bid;     // [wbuf] id | kExpanded
-  int32_t* brnk;     // [wbuf] ranks of the buffer entries in wkey/wid
   float* q;          // [d_pad] FP32 query (rerank, PQ tables)
   float* rk;         // [ef_cap] rerank keys
   float* lut;        // [pq_m * 256] PQ lookup table
@@ -150,7 +149,6 @@ __device__ Lds carve(char* base, const SearchParams& p) {
   s.rnk = (int32_t*)take(sizeof(int32_t) * 64);
   s.bkey = (float*)take(sizeof(float) * p.wbuf);
   s.bid = (uint32_t*)take(sizeof(uint32_t) * p.wbuf);
-  s.brnk = (int32_t*)take(sizeof(int32_t) * p.wbuf);
   s.q = (float*)take(sizeof(float) * p.q_lds_floats);
   s.rk = (float*)take(sizeof(float) * rerank_slots(p));
   s.lut = (float*)take(sizeof(float) * (p.mode == MODE_PQ ? p.pq_m * 256 : 0));
@@ -215,7 +213,7 @@ struct Dense {
   static constexpr int U = (ANN_ROW_CHUNKS / CPL) > 0 ? ANN_ROW_CHUNKS / CPL : 1;  // passes in flight
   float qreg[CPL][C];
 
-  __device__ bool prep(const SearchParams& p, const Lds& s, int64_t q) {
+  __device__ __forceinline__ bool prep(const SearchParams& p, const Lds& s, int64_t q) {
     const int j = lane_id() & (L - 1);
     const float* qrow = p.queries + (size_t)q * p.d;
 #pragma unroll
@@ -232,7 +230,7 @@ struct Dense {
 
   // keys of the m candidate ids in s.cid[] into s.ckey[]
   template <bool IP>
-  __device__ void score_impl(const SearchParams& p, const Lds& s, int m) {
+  __device__ __forceinline__ void score_impl(const SearchParams& p, const Lds& s, int m) {
     const int lane = lane_id();
     const int j = lane & (L - 1);
     const int grp = lane / L;
@@ -293,7 +291,7 @@ struct Dense {
     }
   }
 
-  __device__ void score(const SearchParams& p, const Lds& s, int m) {
+  __device__ __forceinline__ void score(const SearchParams& p, const Lds& s, int m) {
     if (p.metric == METRIC_IP) score_impl<true>(p, s, m);
     else score_impl<false>(p, s, m);
   }
@@ -304,7 +302,7 @@ struct Dense {
 // ----------------------------------------------------------------------------
 
 struct PQ {
-  __device__ bool prep(const SearchParams& p, const Lds& s, int64_t q) {
+  __device__ __forceinline__ bool prep(const SearchParams& p, const Lds& s, int64_t q) {
     const int ds = p.pq_dsub;
     const int entries = p.pq_m * 256;
     const bool ip = p.metric == METRIC_IP;
@@ -327,7 +325,7 @@ struct PQ {
     return true;
   }
 
-  __device__ void score(const SearchParams& p, const Lds& s, int m) {
+  __device__ __forceinline__ void score(const SearchParams& p, const Lds& s, int m) {
     const int per = (m + num_waves() - 1) / num_waves();
     const int ci = wave_id() * per + lane_id();
     if (lane_id() < per && ci < m) {
@@ -364,7 +362,7 @@ __device__ __forceinline__ uint32_t hash_slot(uint32_t t) {
 }
 
 struct Sparse {
-  __device__ bool prep(const SearchParams& p, const Lds& s, int64_t q) {
+  __device__ __forceinline__ bool prep(const SearchParams& p, const Lds& s, int64_t q) {
     for (int i = threadIdx.x; i < kHashSlots; i += blockDim.x) { s.hkey[i] = kHashEmpty; s.hval[i] = 0.0f; }
     __syncthreads();
     const int64_t b = p.q_ptr[q];
@@ -395,7 +393,7 @@ struct Sparse {
     }
   }
 
-  __device__ void score(const SearchParams& p, const Lds& s, int m) {
+  __device__ __forceinline__ void score(const SearchParams& p, const Lds& s, int m) {
     const int lane = lane_id();
     constexpr int U = 8;   // documents in flight
     // every candidate's extent in one round trip
@@ -475,10 +473,11 @@ __device__ int next_unexpanded(const uint32_t* ids, int from, int w) {
   return -1;
 }
 
-// number of entries of a sorted list [0, w) strictly below (k, id)
-__device__ __forceinline__ int rank_in(const float* keys, const uint32_t* ids, int w, float k,
-                                       uint32_t id) {
-  int lo = 0, hi = w;
+// number of entries of a sorted run keys/ids[0, n) strictly below (k, id)
+// (the ids may carry the expanded bit)
+__device__ __forceinline__ int count_below(const float* keys, const uint32_t* ids, int n, float k,
+                                           uint32_t id) {
+  int lo = 0, hi = n;
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
     if (kid_lt(keys[mid], ids[mid] & kIdMask, k, id)) lo = mid + 1;
@@ -487,162 +486,193 @@ __device__ __forceinline__ int rank_in(const float* keys, const uint32_t* ids, i
   return lo;
 }
 
-// Insert the sorted entries nkey/nid[0, mnew) (1 <= mnew <= 64, none equal
-// to an existing one) into the sorted list dkey/did[0, w), keeping the first
-// `cap`; every thread of the workgroup takes part.  Thread j owns old entry j:
-// with a = #{new < old_j} and b = #{new < old_{j+1}} (mnew past the end), old
-// entry j moves to j + a and new entries [a, b) land at j + 1 + i; thread 0
-// also places the new entries below old entry 0.  Chunks of the list go from
-// the highest down, each read completely before it is written; a chunk never
-// writes a position a lower chunk still has to read, and entry j + 1 is read
-// back unchanged after the chunk above it moved.  The walk stops at the chunk
-// that holds the smallest new entry's place.  *r0 receives that place (the
-// position of new entry 0).  Returns the new size.
-__device__ int insert_sorted(float* dkey, uint32_t* did, int w, int cap, const float* nkey,
-                             const uint32_t* nid, int mnew, int32_t* r0) {
+// Merge the sorted run nkey/nid[0, mnew) (mnew >= 1, no entry equal to one
+// of the list) into the sorted list dkey/did[0, w), in place, keeping the
+// first `cap`; every thread of the workgroup takes part.
+//
+// With a_j = #{new < old_j}, old entry j moves to j + a_j and the new entries
+// i in [a_j, a_{j+1}) land at j + 1 + i (a_w = mnew); new entries below old
+// entry 0 stay at i.  Each thread owns E consecutive old entries of a chunk
+// of E x nthr; chunks go from the highest down, each read completely (with
+// the entry just above it) before it is written.  Writes of a chunk land at
+// or above its own entries' positions, so nothing a lower chunk still reads
+// is overwritten, and the entry above a chunk is read back unchanged.  The
+// walk stops at the chunk holding the place of the smallest new entry; the
+// entries below it do not move.
+//
+// *r0 receives the position of new entry 0.  When `hint` is given it is a
+// position of the list before which every entry is expanded, and on return a
+// position of the merged list with the same property: the smallest of where
+// old entry *hint went and where each new entry without the expanded bit
+// went (tracked with atomicMin in *hmin, which must hold INT32_MAX).
+// Returns the new size.
+template <int E>
+__device__ __forceinline__ int merge_sorted(float* dkey, uint32_t* did, int w, int cap, const float* nkey,
+                            const uint32_t* nid, int mnew, int32_t* r0, int* hint, int32_t* hmin) {
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
-  const float k0 = nkey[0];
-  const uint32_t i0 = nid[0];
+  const int h = hint ? *hint : 0;
+  int lowest = w;
   if (w == 0) {
-    if (tid < mnew && tid < cap) { dkey[tid] = nkey[tid]; did[tid] = nid[tid]; }
+    for (int i = tid; i < mnew && i < cap; i += nthr) {
+      dkey[i] = nkey[i];
+      did[i] = nid[i];
+      if (hint && !(nid[i] & kExpanded)) atomicMin(hmin, i);
+    }
     if (tid == 0) *r0 = 0;
     __syncthreads();
-    return mnew < cap ? mnew : cap;
-  }
-  for (int j0 = ((w - 1) / nthr) * nthr; j0 >= 0; j0 -= nthr) {
-    const int j = j0 + tid;
-    float ok = 0.0f;
-    uint32_t oi = 0u;
-    int a = 0, b = 0;
-    if (j < w) {
-      ok = dkey[j];
-      oi = did[j];
-      const uint32_t om = oi & kIdMask;
-      float nk1 = 0.0f;
-      uint32_t ni1 = 0u;
-      const bool last = j + 1 >= w;
-      if (!last) { nk1 = dkey[j + 1]; ni1 = did[j + 1] & kIdMask; }
-      b = last ? mnew : 0;
-      for (int i = 0; i < mnew; ++i) {
-        const float kk = nkey[i];
-        const uint32_t ii = nid[i];
-        a += kid_lt(kk, ii, ok, om) ? 1 : 0;
-        if (!last) b += kid_lt(kk, ii, nk1, ni1) ? 1 : 0;
+  } else {
+    const float k0 = nkey[0];
+    const uint32_t i0 = nid[0] & kIdMask;
+    const int CH = E * nthr;
+    for (int j0 = ((w - 1) / CH) * CH; j0 >= 0; j0 -= CH) {
+      const int jb = j0 + tid * E;
+      float ok[E];
+      uint32_t oi[E];
+      int a[E + 1];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        ok[e] = 0.0f;
+        oi[e] = 0u;
+        if (jb + e < w) { ok[e] = dkey[jb + e]; oi[e] = did[jb + e]; }
       }
-    }
-    // stop below this chunk when its lowest entry is already below every new one
-    const bool more = j0 > 0 && !kid_lt(dkey[j0], did[j0] & kIdMask, k0, i0);
-    __syncthreads();
-    if (j < w) {
-      if (j + a < cap) { dkey[j + a] = ok; did[j + a] = oi; }
-      for (int i = a; i < b; ++i) {
-        const int pos = j + 1 + i;
-        if (pos < cap) { dkey[pos] = nkey[i]; did[pos] = nid[i]; }
+      float nk = 0.0f;
+      uint32_t ni = 0u;
+      const bool has_next = jb + E < w;
+      if (has_next) { nk = dkey[jb + E]; ni = did[jb + E] & kIdMask; }
+      // a[e]: new entries below old entry jb + e; a[E]: below the entry after the block
+      int c = jb < w ? count_below(nkey, nid, mnew, ok[0], oi[0] & kIdMask) : 0;
+      a[0] = c;
+#pragma unroll
+      for (int e = 1; e < E; ++e) {
+        if (jb + e < w)
+          while (c < mnew && kid_lt(nkey[c], nid[c] & kIdMask, ok[e], oi[e] & kIdMask)) ++c;
+        a[e] = c;
       }
-      if (a == 0 && b > 0) *r0 = j + 1;
-      if (j == 0) {
-        for (int i = 0; i < a; ++i)
-          if (i < cap) { dkey[i] = nkey[i]; did[i] = nid[i]; }
-        if (a > 0) *r0 = 0;
+      if (has_next) {
+        while (c < mnew && kid_lt(nkey[c], nid[c] & kIdMask, nk, ni)) ++c;
+        a[E] = c;
+      } else {
+        a[E] = mnew;
       }
-    }
-    __syncthreads();
-    if (!more) break;
-  }
-  const int nw = w + mnew;
-  return nw < cap ? nw : cap;
-}
-
-// Merge the sorted entries nkey/nid[0, mnew), whose ranks in the sorted list
-// dkey/did[0, w) are nrnk[0, mnew) (non-decreasing, r0 = nrnk[0]), into that
-// list, keeping the first `cap`; every thread of the workgroup takes part.
-// The tail [r0, w) moves up by the number of new entries ranked at or below
-// each position; chunks go from the highest down, each read completely before
-// it is written.  Returns the new size.
-__device__ int merge_ranked(float* dkey, uint32_t* did, int w, int cap, const float* nkey,
-                            const uint32_t* nid, const int32_t* nrnk, int mnew, int r0) {
-  const int tid = threadIdx.x;
-  const int nthr = blockDim.x;
-  if (w > r0) {
-    const int top = r0 + ((w - 1 - r0) / nthr) * nthr;
-    for (int j0 = top; j0 >= r0; j0 -= nthr) {
-      const int j = j0 + tid;
-      float wk = 0.0f;
-      uint32_t wi = 0u;
-      int dest = cap;
-      if (j < w) {
-        wk = dkey[j];
-        wi = did[j];
-        int lo = 0, hi = mnew;        // new entries ranked at or below j
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (nrnk[mid] <= j) lo = mid + 1; else hi = mid;
+      const bool more = j0 > 0 && !kid_lt(dkey[j0], did[j0] & kIdMask, k0, i0);
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int j = jb + e;
+        if (j < w) {
+          const int ae = a[e];
+          const int be = j + 1 < w ? a[e + 1] : mnew;
+          if (j + ae < cap) { dkey[j + ae] = ok[e]; did[j + ae] = oi[e]; }
+          if (hint && j == h) atomicMin(hmin, j + ae);
+          for (int i = ae; i < be; ++i) {
+            const int pos = j + 1 + i;
+            if (pos < cap) {
+              dkey[pos] = nkey[i];
+              did[pos] = nid[i];
+              if (hint && !(nid[i] & kExpanded)) atomicMin(hmin, pos);
+            }
+          }
+          if (ae == 0 && be > 0) *r0 = j + 1;
+          if (j == 0) {
+            for (int i = 0; i < ae && i < cap; ++i) {
+              dkey[i] = nkey[i];
+              did[i] = nid[i];
+              if (hint && !(nid[i] & kExpanded)) atomicMin(hmin, i);
+            }
+            if (ae > 0) *r0 = 0;
+          }
         }
-        dest = j + lo;
       }
       __syncthreads();
-      if (j < w && dest < cap) { dkey[dest] = wk; did[dest] = wi; }
-      __syncthreads();
+      lowest = j0;
+      if (!more) break;
     }
   }
-  for (int i = tid; i < mnew; i += nthr) {
-    const int pos = nrnk[i] + i;
-    if (pos < cap) { dkey[pos] = nkey[i]; did[pos] = nid[i]; }
+  const int nw = w + mnew < cap ? w + mnew : cap;
+  if (hint) {
+    int hm = *hmin;
+    if (h >= w) hm = hm < w + mnew ? hm : w + mnew;   // every old entry was expanded
+    else if (h < lowest) hm = hm < h ? hm : h;         // old entry h did not move
+    *hint = hm < nw ? hm : nw;
   }
-  __syncthreads();
-  const int nw = w + mnew;
-  return nw < cap ? nw : cap;
+  return nw;
 }
 
-// Move the insert buffer [0, wb) into the list [0, wm) (wm + wb <= ef);
-// every thread takes part.  `hint` is a position of the list before which
-// every entry is expanded; it is carried over to the merged list.  Entry i of
-// the buffer lands at brnk[i] + i, list entry j at j + #{i : brnk[i] <= j}.
-// s.ctl[CTL_HINT] must hold INT32_MAX on entry.  Returns the new list size.
-__device__ int flush_buffer(const Lds& s, List L, int wm, int wb, int ef, int& hint) {
-  const int tid = threadIdx.x;
-  const int nthr = blockDim.x;
-  for (int i = tid; i < wb; i += nthr) {
-    const uint32_t bi = s.bid[i];
-    const int r = rank_in(L.key, L.id, wm, s.bkey[i], bi & kIdMask);
-    s.brnk[i] = r;
-    if (!(bi & kExpanded)) atomicMin(&s.ctl[CTL_HINT], r + i);
+// State of the beam at the start of an expansion.
+struct Head {
+  int pm, pb;         // first unexpanded entry of the list / of the buffer, or -1
+  float mk;           // key and id of list entry pm
+  uint32_t mi;
+  float tk;           // worst entry of W (meaningful when W holds ef entries)
+  uint32_t ti;
+};
+
+// Cuts W to the best ef entries of list [0, w) and buffer [0, wb) (buffered
+// beams; at most 64 entries fall out per expansion), and finds the first
+// unexpanded entries and the worst entry of W.  The list's last 64 entries
+// and the 64 entries from `hint` are read in one round trip; lane x tests the
+// cut "x entries from the list, d - x from the buffer", of which exactly one
+// keeps every kept entry below every dropped one.  Every wave computes the
+// same result; nothing is written.
+__device__ __forceinline__ Head beam_head(const Lds& s, List L, int& w, int& wb, int ef, int hint, int hint_b,
+                          bool buffered) {
+  const int lane = lane_id();
+  const int tj = w - 1 - lane;
+  float tk = __builtin_inff();
+  uint32_t ti = kIdMask;
+  if (tj >= 0) { tk = L.key[tj]; ti = L.id[tj] & kIdMask; }
+  const int fj = hint + lane;
+  float fk = 0.0f;
+  uint32_t fi = kExpanded;
+  if (fj < w) { fk = L.key[fj]; fi = L.id[fj]; }
+  int xs = 0;
+  if (buffered && w + wb > ef) {
+    const int d = w + wb - ef;
+    const int x = lane;
+    const int y = d - x;
+    const float pk = __shfl_up(tk, 1, 64);              // list[w - x] from lane x - 1
+    const uint32_t pi = (uint32_t)__shfl_up((int)ti, 1, 64);
+    bool ok = x <= d && x <= w && y <= wb;
+    if (ok && w - x >= 1 && y >= 1) ok = kid_lt(tk, ti, s.bkey[wb - y], s.bid[wb - y] & kIdMask);
+    if (ok && wb - y >= 1 && x >= 1) ok = kid_lt(s.bkey[wb - y - 1], s.bid[wb - y - 1] & kIdMask, pk, pi);
+    const uint64_t mk = ballot(ok);
+    xs = mk ? __builtin_ctzll(mk) : 64;                  // only d = 64 can need x = 64
+    w -= xs;
+    wb -= d - xs;
   }
-  __syncthreads();
-  int h = hint < wm ? hint : wm;
-  {
-    int lo = 0, hi = wb;            // buffer entries placed before list entry h
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (s.brnk[mid] <= h) lo = mid + 1; else hi = mid;
+  Head hd;
+  hd.tk = __builtin_inff();
+  hd.ti = kIdMask;
+  if (w > 0) {
+    if (xs < 64) {
+      hd.tk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tk), xs));
+      hd.ti = (uint32_t)__builtin_amdgcn_readlane((int)ti, xs);
+    } else {
+      hd.tk = L.key[w - 1];
+      hd.ti = L.id[w - 1] & kIdMask;
     }
-    h += lo;
   }
-  const int hb = s.ctl[CTL_HINT];
-  hint = hb < h ? hb : h;
-  return merge_ranked(L.key, L.id, wm, ef, s.bkey, s.bid, s.brnk, wb, s.brnk[0]);
-}
-
-// W is the best ef entries of the list [0, wm) and the buffer [0, wb): drop
-// the d = wm + wb - ef worst ones (0 < d <= 64) from the two tails.  Lane x
-// tests the split "x from the list, d - x from the buffer": exactly one split
-// keeps every kept entry below every dropped one.  Reads only; every wave
-// computes the same sizes.
-__device__ __forceinline__ void cut_to_ef(const Lds& s, List L, int& wm, int& wb, int ef) {
-  const int d = wm + wb - ef;
-  if (d <= 0) return;
-  const int x = lane_id();
-  const int y = d - x;
-  bool ok = x <= d && x <= wm && y <= wb;
-  if (ok && wm - x >= 1 && y >= 1)
-    ok = kid_lt(L.key[wm - x - 1], L.id[wm - x - 1] & kIdMask, s.bkey[wb - y], s.bid[wb - y] & kIdMask);
-  if (ok && wb - y >= 1 && x >= 1)
-    ok = kid_lt(s.bkey[wb - y - 1], s.bid[wb - y - 1] & kIdMask, L.key[wm - x], L.id[wm - x] & kIdMask);
-  const uint64_t mk = ballot(ok);
-  const int xs = mk ? __builtin_ctzll(mk) : 64;   // only d = 64 can need x = 64
-  wm -= xs;
-  wb -= d - xs;
+  if (wb > 0) {
+    const float bk = s.bkey[wb - 1];
+    const uint32_t bi = s.bid[wb - 1] & kIdMask;
+    if (w == 0 || kid_lt(hd.tk, hd.ti, bk, bi)) { hd.tk = bk; hd.ti = bi; }
+  }
+  const uint64_t um = ballot(fj < w && !(fi & kExpanded));
+  hd.pm = -1;
+  hd.mk = 0.0f;
+  hd.mi = 0u;
+  if (um) {
+    const int l = __builtin_ctzll(um);
+    hd.pm = hint + l;
+    hd.mk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fk), l));
+    hd.mi = (uint32_t)__builtin_amdgcn_readlane((int)fi, l) & kIdMask;
+  } else if (hint + 64 < w) {
+    hd.pm = next_unexpanded(L.id, hint + 64, w);
+    if (hd.pm >= 0) { hd.mk = L.key[hd.pm]; hd.mi = L.id[hd.pm] & kIdMask; }
+  }
+  hd.pb = buffered ? next_unexpanded(s.bid, hint_b, wb) : -1;
+  return hd;
 }
 
 // ----------------------------------------------------------------------------
@@ -671,7 +701,7 @@ __device__ __forceinline__ void log_visited(const SearchParams& p, int slot, int
 }
 
 template <class Policy, bool GLIST>
-__device__ void run_query(const SearchParams& p, const Lds& s, Policy& pol, int slot, int64_t q) {
+__device__ __forceinline__ void run_query(const SearchParams& p, const Lds& s, Policy& pol, int slot, int64_t q) {
   const int lane = lane_id();
   const int wave = wave_id();
   const int tid = threadIdx.x;
@@ -764,14 +794,13 @@ __device__ void run_query(const SearchParams& p, const Lds& s, Policy& pol, int 
   int w = 1, wb = 0;
   int hint = 0, hint_b = 0;
   while (true) {
-    if (buffered) cut_to_ef(s, L, w, wb, ef);
-    // best unexpanded entry of W (all waves compute it from the same state)
-    const int pm = next_unexpanded(L.id, hint, w);
-    const int pb = buffered ? next_unexpanded(s.bid, hint_b, wb) : -1;
+    // cut to ef, best unexpanded entry and worst entry of W (all waves
+    // compute them from the same state)
+    const Head hd = beam_head(s, L, w, wb, ef, hint, hint_b, buffered);
+    const int pm = hd.pm, pb = hd.pb;
     if (pm < 0 && pb < 0) break;
-    const bool from_buf =
-        pb >= 0 && (pm < 0 || kid_lt(s.bkey[pb], s.bid[pb] & kIdMask, L.key[pm], L.id[pm] & kIdMask));
-    const int c = (int)((from_buf ? s.bid[pb] : L.id[pm]) & kIdMask);
+    const bool from_buf = pb >= 0 && (pm < 0 || kid_lt(s.bkey[pb], s.bid[pb] & kIdMask, hd.mk, hd.mi));
+    const int c = from_buf ? (int)(s.bid[pb] & kIdMask) : (int)hd.mi;
     hint = pm < 0 ? w : from_buf ? pm : pm + 1;
     hint_b = pb < 0 ? wb : from_buf ? pb + 1 : pb;
     st.expansions += 1;
@@ -804,15 +833,8 @@ __device__ void run_query(const SearchParams& p, const Lds& s, Policy& pol, int 
     if (wave == 0) {
       // the worst entry of a full W bounds what is kept
       const bool full = w + wb >= ef;
-      float tk = __builtin_inff();
-      uint32_t ti = kIdMask;
-      if (full) {
-        if (w > 0) { tk = L.key[w - 1]; ti = L.id[w - 1] & kIdMask; }
-        if (wb > 0 && (w == 0 || kid_lt(tk, ti, s.bkey[wb - 1], s.bid[wb - 1] & kIdMask))) {
-          tk = s.bkey[wb - 1];
-          ti = s.bid[wb - 1] & kIdMask;
-        }
-      }
+      const float tk = hd.tk;
+      const uint32_t ti = hd.ti;
       float kk = __builtin_inff();
       uint32_t ki = kIdMask;
       bool keep = false;
@@ -844,17 +866,19 @@ __device__ void run_query(const SearchParams& p, const Lds& s, Policy& pol, int 
     const int mnew = s.ctl[CTL_M];
     if (mnew > 0) {
       if (!buffered) {
-        w = insert_sorted(L.key, L.id, w, ef, s.ckey, (const uint32_t*)s.cid, mnew, &s.ctl[CTL_R0]);
+        w = merge_sorted<4>(L.key, L.id, w, ef, s.ckey, (const uint32_t*)s.cid, mnew, &s.ctl[CTL_R0],
+                            nullptr, nullptr);
         const int r0 = s.ctl[CTL_R0];
         if (r0 < hint) hint = r0;
       } else {
         if (s.ctl[CTL_FLUSH]) {
-          w = flush_buffer(s, L, w, wb, ef, hint);
+          w = merge_sorted<8>(L.key, L.id, w, ef, s.bkey, s.bid, wb, &s.ctl[CTL_R0], &hint,
+                              &s.ctl[CTL_HINT]);
           wb = 0;
           hint_b = 0;
         }
-        wb = insert_sorted(s.bkey, s.bid, wb, p.wbuf, s.ckey, (const uint32_t*)s.cid, mnew,
-                           &s.ctl[CTL_R0]);
+        wb = merge_sorted<4>(s.bkey, s.bid, wb, p.wbuf, s.ckey, (const uint32_t*)s.cid, mnew,
+                             &s.ctl[CTL_R0], nullptr, nullptr);
         const int r0 = s.ctl[CTL_R0];
         if (r0 < hint_b) hint_b = r0;
       }
@@ -863,7 +887,7 @@ __device__ void run_query(const SearchParams& p, const Lds& s, Policy& pol, int 
   if (buffered && wb > 0) {
     if (tid == 0) s.ctl[CTL_HINT] = 0x7FFFFFFF;
     __syncthreads();
-    w = flush_buffer(s, L, w, wb, ef, hint);
+    w = merge_sorted<8>(L.key, L.id, w, ef, s.bkey, s.bid, wb, &s.ctl[CTL_R0], &hint, &s.ctl[CTL_HINT]);
     wb = 0;
   }
   if (wave == 0 && lane == 0) {
@@ -975,8 +999,16 @@ __device__ void run_query(const SearchParams& p, const Lds& s, Policy& pol, int 
   __syncthreads();
 }
 
+// Waves per SIMD the register allocation must leave room for (4 caps a wave
+// at 128 VGPRs); unset, the compiler chooses.
+#ifdef ANN_WAVES_PER_EU
+#define ANN_OCCUPANCY __attribute__((amdgpu_waves_per_eu(ANN_WAVES_PER_EU)))
+#else
+#define ANN_OCCUPANCY
+#endif
+
 template <class Policy, bool GLIST>
-__global__ void __launch_bounds__(512) search_kernel(SearchParams p) {
+__global__ void __launch_bounds__(512) ANN_OCCUPANCY search_kernel(SearchParams p) {
   extern __shared__ __align__(16) char lds_raw[];
   const Lds s = carve(lds_raw, p);
   Policy pol;
