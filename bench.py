@@ -230,6 +230,11 @@ def main():
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time only the headline mode (for profiler runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="copy BYTES between two device buffers 3 times and exit (the plain "
+                         "copy that scales the HBM traffic counters)")
     ap.add_argument("--sweep", default=None, help="comma-separated ef values: write the sweep file")
     ap.add_argument("--sweep-out", default=None, help="where the sweep JSON goes "
                     "(default profiles/<workload>_ef_sweep.json)")
@@ -242,6 +247,14 @@ def main():
     import torch
     import paper_2501_06121_amd as ann
     assert torch.cuda.is_available(), "needs a GPU"
+    if a.copy_calibration:
+        src = torch.ones(a.copy_calibration, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.copy_calibration, "copies": 3}), flush=True)
+        return
     spec, g, X, Q, gt = load_workload(a.workload, a.nq)
     d, k = X.shape[1], a.k
     t = time.time()
@@ -288,6 +301,12 @@ def main():
     achieved = nbytes / (ms / 1e3) / 1e9
     log(f"{a.mode}+rerank{a.rerank} ef={ef}: {ms:.2f} ms/step, {qps:.0f} QPS, recall {rec}, "
         f"{achieved:.0f} GB/s algorithmic")
+
+    if a.headline_only:
+        print(json.dumps({"mode": a.mode, "ef": ef, "ms_per_step": round(ms, 3), "qps": round(qps, 1),
+                          "recall@10": rec, "algorithmic_bytes_per_launch": nbytes}), flush=True)
+        ix.close()
+        return
 
     # FP32 beside it
     f32 = Timed(ann, torch, ix, "f32", Qd, k, ef32, 0, stream)
