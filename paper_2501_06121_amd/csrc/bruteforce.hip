@@ -4,13 +4,16 @@
 // query among a dataset X of d-dimensional vectors) solved by a full scan:
 //
 // Stage 1 (bf_tiles): a workgroup of 4 wavefronts owns 128 queries and a
-//   contiguous range of base rows.  For each tile of 64 base rows it forms the
-//   128 x 64 block of dot products with v_mfma_f32_16x16x4_f32 (operands
-//   staged through LDS in slices of 16 dimensions), turns them into
-//   approximate keys (-dot, or |x|^2 - 2 dot for L2: |q|^2 is the same for
-//   every row of a query), and merges the survivors of a per-query threshold
-//   into a sorted top-64 list per query held in LDS.  At the end the lists go
-//   to scratch memory: 64 candidates per (query, range).
+//   contiguous range of base rows.  For each tile of 128 base rows it forms
+//   the 128 x 128 block of dot products with v_mfma_f32_16x16x4_f32, each
+//   wave a 64 x 64 quarter (16 accumulator tiles).  Operands pass through LDS
+//   in stages of 32 dimensions, stored k-major so that the MFMA operand reads
+//   are free of bank conflicts; the next stage is loaded into registers while
+//   the current one is multiplied.  The block becomes approximate keys (-dot,
+//   or |x|^2 - 2 dot for L2: |q|^2 is the same for every row of a query) in a
+//   tile that reuses the stage buffers, and each query merges the survivors
+//   of its threshold into a sorted top-64 list in LDS.  At the end the lists
+//   go to scratch memory: 64 candidates per (query, range).
 // Stage 2 (bf_finish): one wavefront per query merges the candidate lists of
 //   all ranges into the approximate top-64, re-scores the best k + 16 with the
 //   FP32 rows in the same fixed order as the search kernel, sorts them by
@@ -29,10 +32,15 @@ namespace ann {
 namespace {
 
 constexpr int BM = 128;     // queries per workgroup
-constexpr int BN = 64;      // base rows per tile
-constexpr int BK = 16;      // dimensions per LDS slice
+constexpr int BN = 128;     // base rows per tile
+constexpr int BK = 32;      // dimensions per stage
 constexpr int KC = 64;      // candidates kept per query and range
 constexpr int kRescore = 16;
+constexpr int LDA = BM + 16;   // k-major stage rows (16 mod 32 banks: conflict-free reads)
+constexpr int LDB = BN + 16;
+constexpr int TLD = BN + 1;    // key tile row length
+constexpr int kStageFloats = 2 * BK * (LDA + LDB);
+static_assert(BM * TLD <= kStageFloats, "the key tile reuses the stage buffers");
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
@@ -83,6 +91,33 @@ __device__ void merge_list(float* lk, int* li, float k, int id) {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Insert the few candidates of lanes `mask` into the sorted list (lk, li)[0..KC)
+// one at a time: the list sits one entry per lane, each candidate's rank is
+// the number of entries below it, and the entries from that rank on move up
+// one lane (the last one drops out).
+__device__ void insert_few(float* lk, int* li, float k, int id, uint64_t mask) {
+  const int lane = threadIdx.x & 63;
+  float ek = lk[lane];
+  int ei = li[lane];
+  for (uint64_t m = mask; m; m &= m - 1) {
+    const int b = __builtin_ctzll(m);
+    const float ck = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(k), b));
+    const int ci = __builtin_amdgcn_readlane(id, b);
+    const float wk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ek), KC - 1));
+    const int wi = __builtin_amdgcn_readlane(ei, KC - 1);
+    if (!kid_less(ck, ci, wk, wi)) continue;        // the list has tightened meanwhile
+    const int rank = __builtin_popcountll(__ballot(kid_less(ek, ei, ck, ci)));
+    const float uk = __shfl_up(ek, 1, 64);
+    const int ui = __shfl_up(ei, 1, 64);
+    if (lane > rank) { ek = uk; ei = ui; }
+    if (lane == rank) { ek = ck; ei = ci; }
+  }
+  __builtin_amdgcn_wave_barrier();
+  lk[lane] = ek;
+  li[lane] = ei;
+  __builtin_amdgcn_wave_barrier();
+}
+
 __global__ void __launch_bounds__(64) bf_norms(const float* X, int64_t n, int d, float* x2) {
   const int64_t r = blockIdx.x;
   if (r >= n) return;
@@ -99,7 +134,7 @@ struct BfParams {
   const float* X;
   const float* x2;       // squared row norms (L2 only)
   int64_t n;
-  int d;
+  int d;                 // multiple of 4
   int metric;
   const float* Q;
   int64_t nq;
@@ -109,102 +144,148 @@ struct BfParams {
   int32_t* cand_id;
 };
 
+// One stage (32 dimensions from k0) of the query block and of a base tile:
+// 4 float4 of each per thread, zero outside the matrices.
+struct StageRegs {
+  float4 q[4];
+  float4 x[4];
+};
+
+__device__ __forceinline__ void load_stage(const BfParams& p, int64_t q0, int64_t t0,
+                                           int64_t r_end, int k0, StageRegs& r) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int idx = tid + 256 * u;       // 1024 float4 per operand: row idx / 8, float4 idx % 8
+    const int row = idx >> 3;
+    const int k = k0 + 4 * (idx & 7);
+    const int64_t qi = q0 + row;
+    const int64_t xi = t0 + row;
+    r.q[u] = (qi < p.nq && k < p.d) ? *(const float4*)(p.Q + qi * p.d + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+    r.x[u] = (xi < r_end && k < p.d) ? *(const float4*)(p.X + xi * p.d + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
+__device__ __forceinline__ void store_stage(float* sa, float* sb, const StageRegs& r) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int idx = tid + 256 * u;
+    const int row = idx >> 3;
+    const int kk = 4 * (idx & 7);
+    sa[(kk + 0) * LDA + row] = r.q[u].x;
+    sa[(kk + 1) * LDA + row] = r.q[u].y;
+    sa[(kk + 2) * LDA + row] = r.q[u].z;
+    sa[(kk + 3) * LDA + row] = r.q[u].w;
+    sb[(kk + 0) * LDB + row] = r.x[u].x;
+    sb[(kk + 1) * LDB + row] = r.x[u].y;
+    sb[(kk + 2) * LDB + row] = r.x[u].z;
+    sb[(kk + 3) * LDB + row] = r.x[u].w;
+  }
+}
+
 __global__ void __launch_bounds__(256) bf_tiles(BfParams p) {
-  __shared__ float sq[2][BM][BK + 1];
-  __shared__ float sx[2][BN][BK + 1];
-  __shared__ float tile[BM][BN + 1];
+  __shared__ float stage[kStageFloats];   // [2][BK][LDA] queries, [2][BK][LDB] rows; later the key tile
   __shared__ float lk[BM][KC];
   __shared__ int li[BM][KC];
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const int lane = tid & 63;
+  const int wq = (wave & 1) * 64;         // this wave's 64 queries of the block
+  const int wx = (wave >> 1) * 64;        // and 64 rows of the tile
   const int64_t q0 = (int64_t)blockIdx.x * BM;
   const int range = blockIdx.y;
   const int64_t r_begin = (int64_t)range * p.rows_per_range;
   const int64_t r_end = r_begin + p.rows_per_range < p.n ? r_begin + p.rows_per_range : p.n;
+  float* const sa = stage;                  // stage buffer b of the queries: sa + b * BK * LDA
+  float* const sb = stage + 2 * BK * LDA;   // of the rows: sb + b * BK * LDB
+  float* const tile = stage;
+  const int nst = (p.d + BK - 1) / BK;
 
   for (int i = tid; i < BM * KC; i += 256) {
     lk[i / KC][i % KC] = __builtin_inff();
     li[i / KC][i % KC] = 0x7FFFFFFF;
   }
-  __syncthreads();
 
+  StageRegs regs;
+  if (r_begin < r_end) load_stage(p, q0, r_begin, r_end, 0, regs);
   for (int64_t t0 = r_begin; t0 < r_end; t0 += BN) {
-    floatx4 acc[2][4];
+    __syncthreads();                      // the previous tile's keys have been read
+    store_stage(sa, sb, regs);
+    __syncthreads();
+    floatx4 acc[4][4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-    // slice loader: 128 x 16 query floats and 64 x 16 base floats
-    auto load_slice = [&](int buf, int k0) {
-      for (int i = tid; i < BM * BK; i += 256) {
-        const int r = i / BK, c = i % BK;
-        const int64_t qi = q0 + r;
-        sq[buf][r][c] = (qi < p.nq && k0 + c < p.d) ? p.Q[qi * p.d + k0 + c] : 0.0f;
-      }
-      for (int i = tid; i < BN * BK; i += 256) {
-        const int r = i / BK, c = i % BK;
-        const int64_t xi = t0 + r;
-        sx[buf][r][c] = (xi < r_end && k0 + c < p.d) ? p.X[xi * p.d + k0 + c] : 0.0f;
-      }
-    };
-    load_slice(0, 0);
-    __syncthreads();
-    int buf = 0;
-    for (int k0 = 0; k0 < p.d; k0 += BK) {
-      if (k0 + BK < p.d) load_slice(buf ^ 1, k0 + BK);
+    for (int s = 0; s < nst; ++s) {
+      const int buf = s & 1;
+      if (s + 1 < nst) load_stage(p, q0, t0, r_end, (s + 1) * BK, regs);
+      const float* A = sa + buf * (BK * LDA);
+      const float* B = sb + buf * (BK * LDB);
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
-        float a[2], b[4];
+        const int kr = kk + (lane >> 4);
+        float av[4], bv[4];
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb) a[rb] = sq[buf][wave * 32 + rb * 16 + (lane & 15)][kk + (lane >> 4)];
+        for (int rb = 0; rb < 4; ++rb) av[rb] = A[kr * LDA + wq + rb * 16 + (lane & 15)];
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) b[cb] = sx[buf][cb * 16 + (lane & 15)][kk + (lane >> 4)];
+        for (int cb = 0; cb < 4; ++cb) bv[cb] = B[kr * LDB + wx + cb * 16 + (lane & 15)];
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
+        for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
           for (int cb = 0; cb < 4; ++cb)
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[rb], bv[cb], acc[rb][cb], 0, 0, 0);
       }
+      if (s + 1 < nst) store_stage(sa + (buf ^ 1) * (BK * LDA), sb + (buf ^ 1) * (BK * LDB), regs);
       __syncthreads();
-      buf ^= 1;
     }
-    // approximate keys into the tile: row 16*rb + 4*(lane/16) + r, col 16*cb + lane%16
+    // approximate keys into the tile: row wq + 16 rb + 4 (lane / 16) + r, col wx + 16 cb + lane % 16
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb)
+      for (int cb = 0; cb < 4; ++cb) {
+        const int col = wx + cb * 16 + (lane & 15);
+        const int64_t xi = t0 + col;
+        const float x2 = (p.metric == METRIC_IP || xi >= r_end) ? 0.0f : p.x2[xi];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = wave * 32 + rb * 16 + 4 * (lane >> 4) + r;
-          const int col = cb * 16 + (lane & 15);
-          const int64_t xi = t0 + col;
+          const int row = wq + rb * 16 + 4 * (lane >> 4) + r;
+          const float dot = acc[rb][cb][r];
           float key = __builtin_inff();
-          if (xi < r_end) {
-            const float dot = acc[rb][cb][r];
-            key = (p.metric == METRIC_IP) ? -dot : p.x2[xi] - 2.0f * dot;
-          }
-          tile[row][col] = key;
+          if (xi < r_end) key = (p.metric == METRIC_IP) ? -dot : x2 - 2.0f * dot;
+          tile[row * TLD + col] = key;
         }
+      }
     __syncthreads();
-    // each wave merges its 32 rows
-    for (int rr = 0; rr < 32; ++rr) {
-      const int row = wave * 32 + rr;
+    // the next tile's first stage is in flight while the lists are merged
+    if (t0 + BN < r_end) load_stage(p, q0, t0 + BN, r_end, 0, regs);
+    // each wave merges its 32 queries, 64 columns at a time
+    for (int rr = 0; rr < BM / 4; ++rr) {
+      const int row = wave * (BM / 4) + rr;
       if (q0 + row >= p.nq) break;
-      const float thr_k = lk[row][KC - 1];
-      const int thr_i = li[row][KC - 1];
-      float k = tile[row][lane];
-      // columns past the range are empty entries (+inf, largest id)
-      int id = (t0 + lane < r_end) ? (int)(t0 + lane) : 0x7FFFFFFF;
-      const bool keep = kid_less(k, id, thr_k, thr_i);
-      if (!__ballot(keep)) continue;
-      if (!keep) { k = __builtin_inff(); id = 0x7FFFFFFF; }
-      merge_list(lk[row], li[row], k, id);
+#pragma unroll
+      for (int half = 0; half < BN / 64; ++half) {
+        const int col = half * 64 + lane;
+        const float thr_k = lk[row][KC - 1];
+        const int thr_i = li[row][KC - 1];
+        float k = tile[row * TLD + col];
+        // columns past the range are empty entries (+inf, largest id)
+        int id = (t0 + col < r_end) ? (int)(t0 + col) : 0x7FFFFFFF;
+        const bool keep = kid_less(k, id, thr_k, thr_i);
+        const uint64_t km = __ballot(keep);
+        if (!km) continue;
+        if (__builtin_popcountll(km) > 8) {
+          if (!keep) { k = __builtin_inff(); id = 0x7FFFFFFF; }
+          merge_list(lk[row], li[row], k, id);
+        } else {
+          insert_few(lk[row], li[row], k, id, km);
+        }
+      }
     }
-    __syncthreads();
   }
+  __syncthreads();
   for (int i = tid; i < BM * KC; i += 256) {
     const int r = i / KC, c = i % KC;
     const int64_t qi = q0 + r;
@@ -315,10 +396,25 @@ __global__ void __launch_bounds__(64) bf_finish(BfFinish p) {
 
 }  // namespace
 
-size_t bruteforce_scratch_bytes(int64_t n, int64_t nq, int k) {
-  (void)k;
-  const int nranges = n < 65536 ? 1 : 8;
-  return (size_t)nq * nranges * KC * 8 + (size_t)n * 4 + 256;
+// Base-row ranges per query block: the workgroups (query blocks x ranges)
+// should fill whole rounds of the compute units.  Picks the smallest range
+// count with the least time, counting time as rounds x rows per range, with
+// ranges of at least 4 tiles.
+static int bf_ranges(int64_t n, int64_t nq, int cu) {
+  const int64_t qb = (nq + BM - 1) / BM;
+  int best = 1;
+  double best_t = 1e300;
+  for (int r = 1; r <= 32; ++r) {
+    if (r > 1 && n / r < 4 * BN) break;
+    const int64_t rounds = (qb * r + cu - 1) / cu;
+    const double t = (double)rounds * (double)((n + r - 1) / r);
+    if (t < best_t * 0.99) { best_t = t; best = r; }
+  }
+  return best;
+}
+
+static size_t bruteforce_scratch_bytes(int64_t n, int64_t nq, int nranges) {
+  return (size_t)nq * nranges * KC * 8 + (((size_t)n * 4 + 255) & ~size_t(255)) + 256;
 }
 
 }  // namespace ann
@@ -332,14 +428,15 @@ extern "C" int ann_bruteforce(const ann_index* cix, const float* queries, int64_
   ann_index* ix = const_cast<ann_index*>(cix);
   if (!ix->x_f32) return fail(ANN_EUNSUP, "brute force needs the FP32 rows");
   if (k < 1 || k > KC - kRescore) return fail(ANN_EINVAL, "k %d outside [1, %d]", k, KC - kRescore);
+  if (ix->d % 4 != 0) return fail(ANN_EUNSUP, "brute force needs d %% 4 == 0 (d=%d)", ix->d);
   if (nq < 0) return fail(ANN_EINVAL, "nq < 0");
   if (nq == 0) return ANN_OK;
   if (!queries || !out_ids || !out_dists) return fail(ANN_EINVAL, "NULL pointer");
   std::lock_guard<std::mutex> lock(ix->mu);
   HIP_OR_RETURN(hipSetDevice(ix->device), "hipSetDevice");
   hipStream_t st = stream ? (hipStream_t)stream : ix->stream;
-  const int nranges = ix->n < 65536 ? 1 : 8;
-  const size_t need = bruteforce_scratch_bytes(ix->n, nq, k);
+  const int nranges = bf_ranges(ix->n, nq, ix->cu_count > 0 ? ix->cu_count : 256);
+  const size_t need = bruteforce_scratch_bytes(ix->n, nq, nranges);
   if (ix->bf_scratch_bytes < need) {
     if (ix->bf_scratch) {
       HIP_OR_RETURN(hipStreamSynchronize(st), "hipStreamSynchronize");

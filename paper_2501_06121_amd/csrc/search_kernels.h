@@ -83,10 +83,5 @@ const void* symbol_fp8(const SearchParams& p);
 const void* symbol_pq(const SearchParams& p);
 const void* symbol_sparse(const SearchParams& p);
 
-// brute force on matrix cores
-hipError_t launch_bruteforce(const float* X, int64_t n, int d, int metric, const float* Q,
-                             int64_t nq, int k, int64_t* out_ids, float* out_dists,
-                             void* scratch, size_t scratch_bytes, hipStream_t st);
-size_t bruteforce_scratch_bytes(int64_t n, int64_t nq, int k);
 
 }  // namespace ann

@@ -37,12 +37,17 @@ def test_bruteforce_ip_768(vmf_small):
 
 
 def test_bruteforce_ragged_and_tiny():
-    # n not a multiple of the 64-row tile, nq not a multiple of 128, n < k
+    # n not a multiple of the 128-row tile, nq not a multiple of 128, n < k
     rng = np.random.default_rng(3)
     X = rng.standard_normal((1000 + 37, 64)).astype(np.float32)
     Q = rng.standard_normal((131, 64)).astype(np.float32)
     g = oracle.hnsw_build(X, "ip", 8, 32, np.zeros(X.shape[0]))
     check(X, Q, "ip", 10, g)
+    # d not a multiple of the 32-dimension stage (the last stage is half empty)
+    X48 = rng.standard_normal((777, 48)).astype(np.float32)
+    Q48 = rng.standard_normal((300, 48)).astype(np.float32)
+    g48 = oracle.hnsw_build(X48, "l2", 8, 32, np.zeros(X48.shape[0]))
+    check(X48, Q48, "l2", 16, g48)
     Xs = X[:5]
     gs = oracle.hnsw_build(Xs, "l2", 4, 8, np.zeros(5))
     ix = ann.ann_index_create(gs, "l2", 64, x_f32=Xs)
