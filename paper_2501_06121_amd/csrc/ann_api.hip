@@ -171,13 +171,14 @@ int ensure_workspace(ann_index* ix, Workspace& ws, int64_t slots, int64_t beam_c
   HIP_OR_RETURN(hipMalloc((void**)&ws.counter, 64), "hipMalloc (counter)");
   HIP_OR_RETURN(hipEventCreateWithFlags(&ws.done, hipEventDisableTiming), "hipEventCreate");
   if (beam_cap > 0) {
-    HIP_OR_RETURN(hipMalloc((void**)&ws.beam_key, (size_t)slots * beam_cap * 4), "hipMalloc (beam keys)");
-    HIP_OR_RETURN(hipMalloc((void**)&ws.beam_id, (size_t)slots * beam_cap * 4), "hipMalloc (beam ids)");
+    // two arrays per slot: a buffer flush writes the merged list into the other one
+    HIP_OR_RETURN(hipMalloc((void**)&ws.beam_key, (size_t)slots * beam_cap * 8), "hipMalloc (beam keys)");
+    HIP_OR_RETURN(hipMalloc((void**)&ws.beam_id, (size_t)slots * beam_cap * 8), "hipMalloc (beam ids)");
   }
   ws.slots = slots;
   ws.beam_cap = beam_cap;
   ws.used = false;
-  ws.bytes = slots * ws.bits_words * 4 + slots * (int64_t)ws.vlog_cap * 4 + 64 + slots * beam_cap * 8;
+  ws.bytes = slots * ws.bits_words * 4 + slots * (int64_t)ws.vlog_cap * 4 + 64 + slots * beam_cap * 16;
   return ANN_OK;
 }
 
@@ -295,10 +296,13 @@ int make_params(const ann_index* ix, const ann_batch* b, SearchParams* P) {
     }
     if (wb < 64) P->wbuf = 0;
   }
+  // a beam list in HBM leaves the LDS nearly free: many queries per compute
+  // unit, two waves each (measured best for wide beams)
+  if (P->glist && !cfg.waves_per_query) P->waves_per_query = 2;
   if (lds_bytes(*P) > ix->lds_limit)
     return fail(ANN_EBUDGET, "on-chip memory for ef %d in mode %d: %zu bytes > %zu", ef_cap, mode,
                 lds_bytes(*P), ix->lds_limit);
-  if (!cfg.waves_per_query) P->waves_per_query = default_waves(ix, *P);
+  if (!cfg.waves_per_query && !P->glist) P->waves_per_query = default_waves(ix, *P);
   return ANN_OK;
 }
 
@@ -306,9 +310,6 @@ int make_params(const ann_index* ix, const ann_batch* b, SearchParams* P) {
 // many queries a compute unit holds: the spare wave slots then gather rows
 // for the resident queries.
 int default_waves(const ann_index* ix, const SearchParams& P) {
-  // a beam list in HBM leaves the LDS nearly free: many queries per compute
-  // unit, two waves each (measured best for wide beams)
-  if (P.glist) return 2;
   const void* fn = kernel_symbol(P);
   if (!fn) return 1;
   int with_lds = 0, without = 0;
@@ -330,7 +331,7 @@ int64_t pick_slots(const ann_index* ix, const SearchParams& P, int64_t requested
   if (per_cu <= 0) per_cu = 4;
   int64_t slots = requested > 0 ? requested : (int64_t)ix->cu_count * per_cu;
   // bound the visited bitsets (and HBM beam lists) to 4 GiB
-  const int64_t per_slot = slot_bytes(ix->n) + (P.glist ? (int64_t)P.ef_cap * 8 : 0);
+  const int64_t per_slot = slot_bytes(ix->n) + (P.glist ? (int64_t)P.ef_cap * 16 : 0);
   slots = std::min<int64_t>(slots, std::max<int64_t>(1, (int64_t(4) << 30) / per_slot));
   slots = std::min<int64_t>(slots, std::max<int64_t>(1, P.nq));
   return std::max<int64_t>(1, slots);

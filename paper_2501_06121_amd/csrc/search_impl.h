@@ -40,12 +40,13 @@ namespace ann {
 
 // 16-byte chunks each lane keeps in flight while scoring rows (4 VGPRs each).
 #ifndef ANN_ROW_CHUNKS
-#define ANN_ROW_CHUNKS 16
+#define ANN_ROW_CHUNKS 12
 #endif
 
 constexpr uint32_t kExpanded = 0x80000000u;
 constexpr uint32_t kIdMask = 0x7FFFFFFFu;
 constexpr int kHashSlots = kSparseHashSlots;  // sparse query table (<= 256 terms)
+constexpr int kTailCache = kListTailCache;    // entries of an HBM list's tail kept per wave
 constexpr uint32_t kHashEmpty = 0xFFFFFFFFu;
 
 // ----------------------------------------------------------------------------
@@ -124,6 +125,8 @@ struct Lds {
   int32_t* rnk;      // [64] insertion ranks
   float* bkey;       // [wbuf] insert buffer of a large beam
   uint32_t* bid;     // [wbuf] id | kExpanded
+  float* tck;        // [waves][kTailCache] per-wave copy of an HBM list's tail
+  uint32_t* tci;     // [waves][kTailCache] (ids without the expanded bit)
   float* q;          // [d_pad] FP32 query (rerank, PQ tables)
   float* rk;         // [ef_cap] rerank keys
   float* lut;        // [pq_m * 256] PQ lookup table
@@ -149,6 +152,9 @@ __device__ Lds carve(char* base, const SearchParams& p) {
   s.rnk = (int32_t*)take(sizeof(int32_t) * 64);
   s.bkey = (float*)take(sizeof(float) * p.wbuf);
   s.bid = (uint32_t*)take(sizeof(uint32_t) * p.wbuf);
+  const size_t tail = p.glist ? (size_t)kTailCache * p.waves_per_query : 0;
+  s.tck = (float*)take(sizeof(float) * tail);
+  s.tci = (uint32_t*)take(sizeof(uint32_t) * tail);
   s.q = (float*)take(sizeof(float) * p.q_lds_floats);
   s.rk = (float*)take(sizeof(float) * rerank_slots(p));
   s.lut = (float*)take(sizeof(float) * (p.mode == MODE_PQ ? p.pq_m * 256 : 0));
@@ -599,6 +605,89 @@ __device__ __forceinline__ int merge_sorted(float* dkey, uint32_t* did, int w, i
   return nw;
 }
 
+// Merge the sorted list skey/sid[0, w) and the sorted run nkey/nid[0, mnew)
+// into another array dkey/did, keeping the first `cap` (the buffer flush of a
+// beam list in HBM, which alternates between two arrays).  The placement is
+// that of merge_sorted; source and destination differ, so no chunk order is
+// needed: each thread walks its blocks of E entries (stride E x nthr) with
+// the next block's loads in flight.  `hint` is carried over as in
+// merge_sorted (*hmin must hold INT32_MAX).  Returns the new size.
+template <int E>
+__device__ __forceinline__ int merge_copy(const float* skey, const uint32_t* sid, int w, float* dkey,
+                                          uint32_t* did, int cap, const float* nkey,
+                                          const uint32_t* nid, int mnew, int* hint, int32_t* hmin) {
+  const int tid = threadIdx.x;
+  const int nthr = blockDim.x;
+  const int h = *hint;
+  const int stride = E * nthr;
+  // new entries below old entry 0 (all of them when the list is empty)
+  const int below0 = w > 0 ? count_below(nkey, nid, mnew, skey[0], sid[0] & kIdMask) : mnew;
+  for (int i = tid; i < below0 && i < cap; i += nthr) {
+    dkey[i] = nkey[i];
+    did[i] = nid[i];
+    if (!(nid[i] & kExpanded)) atomicMin(hmin, i);
+  }
+  float ok[E], pk[E];
+  uint32_t oi[E], pi[E];
+  float nk = 0.0f, qk = 0.0f;
+  uint32_t ni = 0u, qi = 0u;
+  auto load = [&](int jb, float* k, uint32_t* id, float& ek, uint32_t& ei) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      k[e] = 0.0f;
+      id[e] = 0u;
+      if (jb + e < w) { k[e] = skey[jb + e]; id[e] = sid[jb + e]; }
+    }
+    ek = 0.0f;
+    ei = 0u;
+    if (jb + E < w) { ek = skey[jb + E]; ei = sid[jb + E] & kIdMask; }
+  };
+  int jb = tid * E;
+  if (jb < w) load(jb, ok, oi, nk, ni);
+  for (; jb < w; jb += stride) {
+    const bool more = jb + stride < w;
+    if (more) load(jb + stride, pk, pi, qk, qi);
+    int c = count_below(nkey, nid, mnew, ok[0], oi[0] & kIdMask);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int j = jb + e;
+      if (j < w) {
+        const int ae = c;
+        int be = mnew;                    // new entries below old entry j + 1
+        if (j + 1 < w) {
+          const float k1 = e + 1 < E ? ok[e + 1] : nk;
+          const uint32_t i1 = (e + 1 < E ? oi[e + 1] : ni) & kIdMask;
+          be = c;
+          while (be < mnew && kid_lt(nkey[be], nid[be] & kIdMask, k1, i1)) ++be;
+        }
+        if (j + ae < cap) { dkey[j + ae] = ok[e]; did[j + ae] = oi[e]; }
+        if (j == h) atomicMin(hmin, j + ae);
+        for (int i = ae; i < be; ++i) {
+          const int pos = j + 1 + i;
+          if (pos < cap) {
+            dkey[pos] = nkey[i];
+            did[pos] = nid[i];
+            if (!(nid[i] & kExpanded)) atomicMin(hmin, pos);
+          }
+        }
+        c = be;
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) { ok[e] = pk[e]; oi[e] = pi[e]; }
+      nk = qk;
+      ni = qi;
+    }
+  }
+  __syncthreads();
+  const int nw = w + mnew < cap ? w + mnew : cap;
+  int hm = *hmin;
+  if (h >= w) hm = hm < w + mnew ? hm : w + mnew;   // every old entry was expanded
+  *hint = hm < nw ? hm : nw;
+  return nw;
+}
+
 // State of the beam at the start of an expansion.
 struct Head {
   int pm, pb;         // first unexpanded entry of the list / of the buffer, or -1
@@ -608,24 +697,68 @@ struct Head {
   uint32_t ti;
 };
 
+// What a wave keeps of a beam list in HBM between expansions.  Between buffer
+// flushes the list only loses entries at its end (cuts) and gains expanded
+// bits before the scan position, so a window of 64 entries from the scan
+// position (in registers, lane l holding entry wh + l) and a copy of the last
+// kTailCache entries (in the wave's LDS, from entry tw on) stay valid until
+// the scan leaves the window or the cuts reach the copy's start.  A flush
+// rewrites the list: both are then marked stale.
+struct ListCache {
+  int wh;          // list position of the window's lane 0, -1 when stale
+  int tw;          // list position of the tail copy's entry 0, -1 when stale
+  float fk;        // this lane's window entry
+  uint32_t fi;
+};
+
 // Cuts W to the best ef entries of list [0, w) and buffer [0, wb) (buffered
 // beams; at most 64 entries fall out per expansion), and finds the first
-// unexpanded entries and the worst entry of W.  The list's last 64 entries
-// and the 64 entries from `hint` are read in one round trip; lane x tests the
-// cut "x entries from the list, d - x from the buffer", of which exactly one
-// keeps every kept entry below every dropped one.  Every wave computes the
-// same result; nothing is written.
-__device__ __forceinline__ Head beam_head(const Lds& s, List L, int& w, int& wb, int ef, int hint, int hint_b,
-                          bool buffered) {
+// unexpanded entries and the worst entry of W.  Lane x tests the cut "x
+// entries from the list, d - x from the buffer", of which exactly one keeps
+// every kept entry below every dropped one; it needs list entries w - 1 - x,
+// which an LDS list provides directly and an HBM list through the wave's
+// caches (refilled in one round trip when they run out).  Every wave computes
+// the same result; nothing shared is written.
+template <bool GLIST>
+__device__ __forceinline__ Head beam_head(const Lds& s, List L, int& w, int& wb, int ef, int hint,
+                                          int hint_b, bool buffered, ListCache& lc) {
   const int lane = lane_id();
   const int tj = w - 1 - lane;
   float tk = __builtin_inff();
   uint32_t ti = kIdMask;
-  if (tj >= 0) { tk = L.key[tj]; ti = L.id[tj] & kIdMask; }
-  const int fj = hint + lane;
-  float fk = 0.0f;
-  uint32_t fi = kExpanded;
-  if (fj < w) { fk = L.key[fj]; fi = L.id[fj]; }
+  int fj;
+  float fk;
+  uint32_t fi;
+  if constexpr (GLIST) {
+    float* ck = s.tck + wave_id() * kTailCache;
+    uint32_t* ci = s.tci + wave_id() * kTailCache;
+    if (lc.tw < 0 || w - 64 < lc.tw) {
+      const int tw = w > kTailCache ? w - kTailCache : 0;
+#pragma unroll
+      for (int r = 0; r < kTailCache / 64; ++r) {
+        const int j = tw + lane + 64 * r;
+        if (j < w) { ck[j - tw] = L.key[j]; ci[j - tw] = L.id[j] & kIdMask; }
+      }
+      lc.tw = tw;
+      wave_sync();
+    }
+    if (tj >= 0) { tk = ck[tj - lc.tw]; ti = ci[tj - lc.tw]; }
+    if (lc.wh < 0 || hint < lc.wh || hint >= lc.wh + 64) {
+      lc.wh = hint;
+      lc.fk = 0.0f;
+      lc.fi = kExpanded;
+      if (hint + lane < w) { lc.fk = L.key[hint + lane]; lc.fi = L.id[hint + lane]; }
+    }
+    fj = lc.wh + lane;
+    fk = lc.fk;
+    fi = lc.fi;
+  } else {
+    if (tj >= 0) { tk = L.key[tj]; ti = L.id[tj] & kIdMask; }
+    fj = hint + lane;
+    fk = 0.0f;
+    fi = kExpanded;
+    if (fj < w) { fk = L.key[fj]; fi = L.id[fj]; }
+  }
   int xs = 0;
   if (buffered && w + wb > ef) {
     const int d = w + wb - ef;
@@ -658,18 +791,20 @@ __device__ __forceinline__ Head beam_head(const Lds& s, List L, int& w, int& wb,
     const uint32_t bi = s.bid[wb - 1] & kIdMask;
     if (w == 0 || kid_lt(hd.tk, hd.ti, bk, bi)) { hd.tk = bk; hd.ti = bi; }
   }
-  const uint64_t um = ballot(fj < w && !(fi & kExpanded));
+  const uint64_t um = ballot(fj >= hint && fj < w && !(fi & kExpanded));
   hd.pm = -1;
   hd.mk = 0.0f;
   hd.mi = 0u;
   if (um) {
     const int l = __builtin_ctzll(um);
-    hd.pm = hint + l;
+    hd.pm = fj - lane + l;
     hd.mk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fk), l));
     hd.mi = (uint32_t)__builtin_amdgcn_readlane((int)fi, l) & kIdMask;
-  } else if (hint + 64 < w) {
-    hd.pm = next_unexpanded(L.id, hint + 64, w);
+  } else if (fj - lane + 64 < w) {
+    // nothing unexpanded in the window: scan on (the window moves with the scan position)
+    hd.pm = next_unexpanded(L.id, fj - lane + 64, w);
     if (hd.pm >= 0) { hd.mk = L.key[hd.pm]; hd.mi = L.id[hd.pm] & kIdMask; }
+    if constexpr (GLIST) lc.wh = -1;
   }
   hd.pb = buffered ? next_unexpanded(s.bid, hint_b, wb) : -1;
   return hd;
@@ -778,13 +913,18 @@ __device__ __forceinline__ void run_query(const SearchParams& p, const Lds& s, P
     const bool isnew = (lane == 0) && !(old & bit);
     log_visited(p, slot, q, st, isnew, cur, ballot(isnew));
   }
-  List L;
+  // the beam list; an HBM list has two arrays per slot and a flush writes
+  // the merged list into the other one (L2)
+  List L, L2;
   if constexpr (GLIST) {
-    L.key = p.glist_key + (size_t)slot * p.ef_cap;
-    L.id = p.glist_id + (size_t)slot * p.ef_cap;
+    L.key = p.glist_key + (size_t)slot * 2 * p.ef_cap;
+    L.id = p.glist_id + (size_t)slot * 2 * p.ef_cap;
+    L2.key = L.key + p.ef_cap;
+    L2.id = L.id + p.ef_cap;
   } else {
     L.key = s.wkey;
     L.id = s.wid;
+    L2 = L;
   }
   if (tid == 0) { L.key[0] = ckey; L.id[0] = (uint32_t)cur; }
   __syncthreads();
@@ -793,10 +933,11 @@ __device__ __forceinline__ void run_query(const SearchParams& p, const Lds& s, P
   const bool buffered = GLIST || (p.wbuf > 0 && ef > p.wbuf_min_ef);
   int w = 1, wb = 0;
   int hint = 0, hint_b = 0;
+  ListCache lc{-1, -1, 0.0f, kExpanded};
   while (true) {
     // cut to ef, best unexpanded entry and worst entry of W (all waves
     // compute them from the same state)
-    const Head hd = beam_head(s, L, w, wb, ef, hint, hint_b, buffered);
+    const Head hd = beam_head<GLIST>(s, L, w, wb, ef, hint, hint_b, buffered, lc);
     const int pm = hd.pm, pb = hd.pb;
     if (pm < 0 && pb < 0) break;
     const bool from_buf = pb >= 0 && (pm < 0 || kid_lt(s.bkey[pb], s.bid[pb] & kIdMask, hd.mk, hd.mi));
@@ -872,10 +1013,20 @@ __device__ __forceinline__ void run_query(const SearchParams& p, const Lds& s, P
         if (r0 < hint) hint = r0;
       } else {
         if (s.ctl[CTL_FLUSH]) {
-          w = merge_sorted<8>(L.key, L.id, w, ef, s.bkey, s.bid, wb, &s.ctl[CTL_R0], &hint,
+          if constexpr (GLIST) {
+            w = merge_copy<4>(L.key, L.id, w, L2.key, L2.id, ef, s.bkey, s.bid, wb, &hint,
                               &s.ctl[CTL_HINT]);
+            const List t = L;
+            L = L2;
+            L2 = t;
+          } else {
+            w = merge_sorted<8>(L.key, L.id, w, ef, s.bkey, s.bid, wb, &s.ctl[CTL_R0], &hint,
+                                &s.ctl[CTL_HINT]);
+          }
           wb = 0;
           hint_b = 0;
+          lc.wh = -1;
+          lc.tw = -1;
         }
         wb = merge_sorted<4>(s.bkey, s.bid, wb, p.wbuf, s.ckey, (const uint32_t*)s.cid, mnew,
                              &s.ctl[CTL_R0], nullptr, nullptr);
@@ -887,7 +1038,12 @@ __device__ __forceinline__ void run_query(const SearchParams& p, const Lds& s, P
   if (buffered && wb > 0) {
     if (tid == 0) s.ctl[CTL_HINT] = 0x7FFFFFFF;
     __syncthreads();
-    w = merge_sorted<8>(L.key, L.id, w, ef, s.bkey, s.bid, wb, &s.ctl[CTL_R0], &hint, &s.ctl[CTL_HINT]);
+    if constexpr (GLIST) {
+      w = merge_copy<4>(L.key, L.id, w, L2.key, L2.id, ef, s.bkey, s.bid, wb, &hint, &s.ctl[CTL_HINT]);
+      L = L2;
+    } else {
+      w = merge_sorted<8>(L.key, L.id, w, ef, s.bkey, s.bid, wb, &s.ctl[CTL_R0], &hint, &s.ctl[CTL_HINT]);
+    }
     wb = 0;
   }
   if (wave == 0 && lane == 0) {

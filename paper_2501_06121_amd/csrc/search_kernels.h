@@ -44,8 +44,8 @@ struct SearchParams {
   int wbuf;                         // insert-buffer entries of a large beam (0: none)
   int wbuf_min_ef;                  // queries with ef above this use the buffer
   int glist;                        // beam list in HBM (glist_key/glist_id) instead of LDS
-  float* glist_key;                 // [slots][ef_cap]
-  uint32_t* glist_id;               // [slots][ef_cap]
+  float* glist_key;                 // [slots][2][ef_cap] (two arrays per slot)
+  uint32_t* glist_id;               // [slots][2][ef_cap]
   int64_t* out_ids;
   float* out_dists;
   int32_t* out_status;
@@ -62,6 +62,8 @@ struct SearchParams {
 
 // Entries of the sparse query's hash table in LDS (at most half filled).
 constexpr int kSparseHashSlots = 512;
+// Entries of a beam list's tail that each wave copies to LDS when the list is in HBM.
+constexpr int kListTailCache = 256;
 
 // Rerank keys held at once: R_eff <= min(max(R, k_max), ef_cap).
 __host__ __device__ inline int rerank_slots(const SearchParams& p) {

@@ -48,6 +48,7 @@ size_t lds_bytes(const SearchParams& p) {
   b += al(p.glist ? 0 : 4 * (size_t)p.ef_cap) * 2;
   b += al(4 * 64) * 3;
   b += al(4 * (size_t)p.wbuf) * 2;
+  b += al(p.glist ? 4 * (size_t)kListTailCache * p.waves_per_query : 0) * 2;
   b += al(4 * (size_t)p.q_lds_floats);
   b += al(4 * (size_t)rerank_slots(p));
   b += al(p.mode == MODE_PQ ? 4 * (size_t)p.pq_m * 256 : 0);

@@ -277,7 +277,7 @@ int ann_server_create(const ann_index* cix, const ann_server_cfg* cfg, ann_serve
   const int64_t batch_bytes = max_batch * ((int64_t)ix->d * 4 + 8 + (int64_t)c.k_max * 12 + 4);
   P.nq = max_batch;
   int64_t slots = pick_slots(ix, P, 0);
-  const int64_t per_slot = slot_bytes(ix->n) + (proto.glist ? (int64_t)proto.ef_cap * 8 : 0);
+  const int64_t per_slot = slot_bytes(ix->n) + (proto.glist ? (int64_t)proto.ef_cap * 16 : 0);
   while (slots > 1 && c.streams * (batch_bytes + slots * per_slot) > c.hbm_budget) slots /= 2;
   if (c.streams * (batch_bytes + slots * per_slot) > c.hbm_budget)
     return fail(ANN_EBUDGET, "hbm_budget %lld too small for one slot per stream", (long long)c.hbm_budget);
