@@ -189,13 +189,22 @@ def serve_latency(ann, ix, Q, k, ef, mode, rerank, qps_peak, seconds=3.0, seed=0
     return float(np.percentile(lat, 50)), float(np.percentile(lat, 99)), rate
 
 
-def cpu_baseline(g, X, Q, mode, ef, k, rerank, budget_s=15.0):
-    """The oracle's search (same mode, ef, rerank) on a sample of queries,
-    all host cores (OpenMP across queries)."""
+def host_threads():
+    """Threads the host gives this process (OMP_NUM_THREADS when set, else the CPUs it may use)."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return int(env)
+    return len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+
+
+def cpu_baseline(g, X, Q, mode, ef, k, rerank, budget_s=15.0, single_s=8.0):
+    """The oracle's search (same mode, ef, rerank) on a sample of queries, on
+    all host threads (OpenMP across queries), and on one thread (the paper's
+    setting) for a shorter sample."""
     import oracle
     g = oracle.Graph(g.n, g.M, g.M0, g.max_level, g.entry, g.levels, g.adj0, g.upper_off,
                      g.upper_adj)
-    threads = os.cpu_count() or 1
+    threads = host_threads()
     if mode == "f16":
         st = oracle.dense_store(X.astype(np.float16).view(np.uint16), "ip", "f16")
     else:
@@ -211,9 +220,19 @@ def cpu_baseline(g, X, Q, mode, ef, k, rerank, budget_s=15.0):
     oracle.hnsw_search(g, st, k, ef, Q=Q[:m], rerank_f32=X if rerank else None, rerank=rerank,
                        threads=threads)
     dt = time.perf_counter() - t
-    return {"value": m / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {m} of {Q.shape[0]} queries, same graph, mode, ef and rerank, "
-                      f"{dt:.1f}s"}
+    out = {"value": m / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {m} of {Q.shape[0]} queries, same graph, mode, ef and rerank, "
+                     f"{dt:.1f}s"}
+    # one thread: as many of the first queries as fit the shorter budget (at least one)
+    n1, t = 0, time.perf_counter()
+    while n1 < Q.shape[0] and (n1 == 0 or time.perf_counter() - t < single_s):
+        oracle.hnsw_search(g, st, k, ef, Q=Q[n1:n1 + 1], rerank_f32=X if rerank else None,
+                           rerank=rerank, threads=1)
+        n1 += 1
+    dt1 = time.perf_counter() - t
+    single = {"value": n1 / dt1, "unit": "queries/s", "threads": 1,
+              "sample": f"first {n1} queries, {dt1:.1f}s"}
+    return out, single
 
 
 def main():
@@ -230,6 +249,7 @@ def main():
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the headline mode (for profiler runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -317,6 +337,24 @@ def main():
     b32 = algorithmic_bytes(st32["stats"].cpu().numpy(), "f32", d, g.M0, k, 0)
     log(f"f32 ef={ef32}: {ms32:.2f} ms/step, {Q.shape[0] / (ms32 / 1e3):.0f} QPS, recall {rec32}")
 
+    # BF16 rows + the same rerank (an extra row beside the headline)
+    bf16_row = None
+    if not a.no_bf16:
+        u = X.view(np.uint32)
+        xb = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)   # round to nearest even
+        ixb = ann.ann_index_create(g, spec["metric"], d, x_f32=X, x_bf16=xb)
+        del xb
+        tb = Timed(ann, torch, ixb, "bf16", Qd, k, ef, a.rerank, stream)
+        msb, _ = tb.run(1, 1)
+        recb = recall(tb.out["ids"].cpu().numpy(), gt, k) if gt is not None else None
+        stb = tb.step(stats=True)
+        torch.cuda.synchronize()
+        bb = algorithmic_bytes(stb["stats"].cpu().numpy(), "bf16", d, g.M0, k, a.rerank)
+        bf16_row = {"ef": ef, "qps": round(Q.shape[0] / (msb / 1e3), 1), "recall@10": recb,
+                    "ms_per_step": round(msb, 3), "algorithmic_GBps": round(bb / (msb / 1e3) / 1e9, 1)}
+        ixb.close()
+        log(f"bf16+rerank{a.rerank} ef={ef}: {msb:.2f} ms/step, {bf16_row['qps']:.0f} QPS, recall {recb}")
+
     # exact k-NN on matrix cores (ground truth path): one launch, all queries
     bf = None
     try:
@@ -340,17 +378,22 @@ def main():
         log(f"bruteforce skipped: {e}")
 
     p50 = p99 = rate = None
+    p50_32 = p99_32 = rate32 = None
     if not a.no_serve:
         try:
             p50, p99, rate = serve_latency(ann, ix, Q, k, ef, a.mode, a.rerank, qps)
             log(f"serving at {rate:.0f} QPS offered: p50 {p50:.2f} ms p99 {p99:.2f} ms")
+            qps32 = Q.shape[0] / (ms32 / 1e3)
+            p50_32, p99_32, rate32 = serve_latency(ann, ix, Q, k, ef32, "f32", 0, qps32)
+            log(f"serving f32 at {rate32:.0f} QPS offered: p50 {p50_32:.2f} ms p99 {p99_32:.2f} ms")
         except ann.AnnError as e:
             log(f"serving skipped: {e}")
 
-    cpu = None
+    cpu = cpu1 = None
     if not a.no_cpu:
-        cpu = cpu_baseline(g, X, Q, a.mode, ef, k, a.rerank)
-        log(f"cpu oracle: {cpu['value']:.1f} QPS on {cpu['cores']} threads")
+        cpu, cpu1 = cpu_baseline(g, X, Q, a.mode, ef, k, a.rerank)
+        log(f"cpu oracle: {cpu['value']:.1f} QPS on {cpu['cores']} threads, "
+            f"{cpu1['value']:.2f} QPS on one thread")
 
     traffic = None
     tp = os.path.join(PROFILES, f"search_{a.workload}_traffic.json")
@@ -384,7 +427,10 @@ def main():
             "p50_ms": p50, "p99_ms": p99, "serve_offered_qps": rate,
             "f32": {"ef": ef32, "qps": round(Q.shape[0] / (ms32 / 1e3), 1), "recall@10": rec32,
                     "ms_per_step": round(ms32, 3),
-                    "algorithmic_GBps": round(b32 / (ms32 / 1e3) / 1e9, 1)},
+                    "algorithmic_GBps": round(b32 / (ms32 / 1e3) / 1e9, 1),
+                    "p50_ms": p50_32, "p99_ms": p99_32, "serve_offered_qps": rate32},
+            "bf16+rerank": bf16_row,
+            "cpu_oracle_single_thread": cpu1,
             "wall_s": round(wall, 3),
             "bruteforce_mfma": bf,
         },
