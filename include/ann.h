@@ -293,6 +293,43 @@ int ann_autotune(ann_index* ix, const ann_batch* b, ann_launch_cfg* best);
 int ann_bruteforce(const ann_index* ix, const float* queries, int64_t nq, int32_t k,
                    int64_t* out_ids, float* out_dists, int32_t* out_certified, void* stream);
 
+/* ---- product quantization on the device -------------------------------- */
+
+/*
+ * Product Quantization (Section 2 of the paper and its citation, Jegou et
+ * al.): the d dimensions are split into m contiguous subspaces of d/m
+ * dimensions (d/m <= 32), each quantized to one of ksub <= 256 centroids.
+ * Distances are squared L2, summed in FP64 from the FP32 inputs in ascending
+ * dimension order (one multiply and one add per dimension); the nearest
+ * centroid is the first minimum (lower index on ties).  The results are
+ * fixed bit for bit by the inputs.
+ *
+ * ann_pq_train: Lloyd's k-means per subspace on the sample rows.  Centroid j
+ * starts at sample point init[j]; each iteration assigns every sample point,
+ * stops a subspace when no assignment changed, and otherwise replaces each
+ * centroid by the FP64 mean of its points (summed in ascending sample order,
+ * rounded once to FP32).  An empty cluster takes the sample point with the
+ * largest error of that iteration (lower sample position on ties, each point
+ * at most once per iteration), clusters in ascending order.
+ *   X              device f32[n][d]
+ *   sample         device i64[ns], row ids into X (ns >= ksub)
+ *   init           device i64[ksub], positions into sample
+ *   out_codebook   device f32[m][ksub][d/m]
+ *   out_iters      optional host i32: iterations run (the largest over the
+ *                  subspaces; max_iter when some subspace never settled)
+ * Allocates its scratch (assignments and errors, 12 bytes per sample point
+ * and subspace) and frees it before returning; synchronizes `stream`.
+ *
+ * ann_pq_encode: codes[r][s] = the nearest centroid of subspace s of row r.
+ *   X device f32[n][d], codebook device f32[m][ksub][d/m], out_codes device
+ *   u8[n][m].  Asynchronous on `stream` (NULL: the null stream, blocking).
+ */
+int ann_pq_train(const float* X, int64_t n, int32_t d, const int64_t* sample, int64_t ns,
+                 const int64_t* init, int32_t m, int32_t ksub, int32_t max_iter,
+                 float* out_codebook, int32_t* out_iters, void* stream);
+int ann_pq_encode(const float* X, int64_t n, int32_t d, const float* codebook, int32_t m,
+                  int32_t ksub, uint8_t* out_codes, void* stream);
+
 /* ---- serving: continuous batching ------------------------------------------ */
 
 typedef struct ann_server ann_server;

@@ -90,6 +90,8 @@ SIGNATURES = {
     "ann_get_launch": ([P, I32, P], C.c_int),
     "ann_autotune": ([P, P, P], C.c_int),
     "ann_bruteforce": ([P, P, I64, I32, P, P, P, P], C.c_int),
+    "ann_pq_train": ([P, I64, I32, P, I64, P, I32, I32, I32, P, P, P], C.c_int),
+    "ann_pq_encode": ([P, I64, I32, P, I32, I32, P, P], C.c_int),
     "ann_server_create": ([P, P, P], C.c_int),
     "ann_server_submit": ([P, P], C.c_int),
     "ann_server_poll": ([P, P, I32], C.c_int),
@@ -361,6 +363,31 @@ def ann_bruteforce(index, queries, k, stream=None):
     _check(lib().ann_bruteforce(index.handle, _dptr(queries), nq, int(k), _dptr(ids), _dptr(dists),
                                 _dptr(cert), _stream_handle(stream)))
     return ids, dists, cert
+
+
+def ann_pq_train(X, sample, init, m, ksub=256, max_iter=25, stream=None):
+    """k-means per subspace on the device.  X: device f32[n, d]; sample, init:
+    device i64 (row ids; positions into sample).  Returns (codebook f32[m, ksub,
+    d/m] on X's device, iterations run)."""
+    torch = _torch()
+    n, d = X.shape
+    cb = torch.empty((m, ksub, d // m), dtype=torch.float32, device=X.device)
+    iters = C.c_int32(0)
+    _check(lib().ann_pq_train(_dptr(X), n, d, _dptr(sample), sample.shape[0], _dptr(init), int(m),
+                              int(ksub), int(max_iter), _dptr(cb), C.byref(iters),
+                              _stream_handle(stream)))
+    return cb, iters.value
+
+
+def ann_pq_encode(X, codebook, stream=None):
+    """Codes u8[n, m] of the rows of X (device f32[n, d]) for a device codebook."""
+    torch = _torch()
+    n, d = X.shape
+    m, ksub, _ = codebook.shape
+    codes = torch.empty((n, m), dtype=torch.uint8, device=X.device)
+    _check(lib().ann_pq_encode(_dptr(X), n, d, _dptr(codebook), int(m), int(ksub), _dptr(codes),
+                               _stream_handle(stream)))
+    return codes
 
 
 # --------------------------------------------------------------------------

@@ -61,6 +61,25 @@ def test_null_arguments_rejected():
     assert L.ann_index_free(None) == ann.ANN_OK
 
 
+def test_pq_arguments_checked_on_the_host():
+    """Shape and pointer checks of the device PQ entry points run before any
+    device call (so they hold without a GPU)."""
+    L = ann.lib()
+    it = C.c_int32(0)
+    # d not a multiple of m, subspaces wider than 32, ksub out of range, NULL pointers
+    assert L.ann_pq_encode(None, 10, 100, None, 3, 256, None, None) == ann.ANN_EINVAL
+    assert L.ann_pq_encode(None, 10, 128, None, 2, 256, None, None) == ann.ANN_EUNSUP
+    assert L.ann_pq_encode(None, 10, 128, None, 16, 257, None, None) == ann.ANN_EINVAL
+    assert L.ann_pq_encode(None, 10, 128, None, 16, 256, None, None) == ann.ANN_EINVAL
+    assert "NULL" in L.ann_last_error().decode()
+    assert L.ann_pq_train(None, 10, 128, None, 100, None, 16, 256, 5, None, C.byref(it), None) == ann.ANN_EINVAL
+    x = np.zeros(4, np.float32)
+    p = x.ctypes.data
+    assert L.ann_pq_train(p, 10, 128, p, 100, p, 16, 256, 5, p, C.byref(it), None) == ann.ANN_EINVAL
+    assert "sample" in L.ann_last_error().decode()          # 100 sample points for 256 centroids
+    assert L.ann_pq_train(p, 10, 128, p, 300, p, 16, 256, 0, p, C.byref(it), None) == ann.ANN_EINVAL
+
+
 class _G:
     def __init__(self, n, M=4, M0=8):
         self.n, self.M, self.M0, self.max_level, self.entry = n, M, M0, 0, 0

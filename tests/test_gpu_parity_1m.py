@@ -135,3 +135,29 @@ def test_quantized_traversal_with_rerank(big, mode):
     assert np.array_equal(stats[sample, 2], ref["stats"][:, 3])
     if big["gt"] is not None:
         say(mode, "recall@10", oracle.recall_at_k(ids, big["gt"], 10))
+
+
+def test_pq_training_and_encoding_at_full_size(big):
+    """PQ 64 x 256 trained on the device with the oracle's sample, init and
+    iteration budget (100,000 sample rows, 25 iterations) equals the oracle's
+    stored codebook bit for bit, and the device codes of all 1,000,000 rows
+    equal the oracle's stored codes."""
+    if big["codes"] is None:
+        pytest.skip("data/vmf1m/pq.npz not built")
+    X = torch.from_numpy(big["X"]).to("cuda:0")
+    sample, init = synth.pq_sample(0, big["X"].shape[0], 100_000, 256)
+    import time
+    say("pq training on the device, 100,000 sample rows, 25 iterations")
+    t = time.perf_counter()
+    cb, iters = ann.ann_pq_train(X, torch.from_numpy(sample).to("cuda:0"),
+                                 torch.from_numpy(init).to("cuda:0"), 64, 256, 25)
+    torch.cuda.synchronize()
+    say(f"trained in {time.perf_counter() - t:.3f} s ({iters} iterations)")
+    assert np.array_equal(cb.cpu().numpy().view(np.uint32), big["cb"].view(np.uint32))
+    say("pq encoding of 1,000,000 rows")
+    cbd = torch.from_numpy(big["cb"]).to("cuda:0")
+    t = time.perf_counter()
+    codes = ann.ann_pq_encode(X, cbd)
+    torch.cuda.synchronize()
+    say(f"encoded in {time.perf_counter() - t:.3f} s")
+    assert np.array_equal(codes.cpu().numpy(), big["codes"])
