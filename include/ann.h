@@ -293,6 +293,44 @@ int ann_autotune(ann_index* ix, const ann_batch* b, ann_launch_cfg* best);
 int ann_bruteforce(const ann_index* ix, const float* queries, int64_t nq, int32_t k,
                    int64_t* out_ids, float* out_dists, int32_t* out_certified, void* stream);
 
+/* ---- HNSW construction on the device ------------------------------------- */
+
+/*
+ * Builds the HNSW graph (the paper's index, Section 2, built as its
+ * citation's Algorithms 1 and 4 describe) over dense FP32 rows, with every
+ * key in the fixed FP32 order above.  Levels: l_i = min(floor(-ln(1 - u_i) /
+ * ln M), 30).  Nodes are inserted in batches: the first seq_prefix one at a
+ * time, then batches of max(1, min(batch_cap, floor(done * batch_frac)))
+ * (batch_frac = 0: one at a time throughout).  Every node of a batch searches
+ * the graph as it was before the batch: greedy descent (ef = 1) down to its
+ * level, then on each layer from min(max level, l_i) to 0 a beam search of
+ * width efc from the previous layer's result, whose best entries are thinned
+ * by the neighbour heuristic (keep a candidate iff it is strictly closer to
+ * the new node than to every kept one; M per layer, layer 0 included).  Then
+ * the batch's reverse links are added, grouped by (target, layer) with the
+ * sources in node order; a list that would exceed 2M entries (layer 0) or M
+ * (above) is sorted by key to its node and cut back by the same heuristic.
+ *   X          device f32[n][d], d a multiple of 4, at most 1024
+ *   u          host f64[n] level uniforms in [0, 1)
+ *   M          2..32 (layer 0 keeps up to 2M)
+ *   efc        1..4096
+ *   out        receives a host-side graph; read it with ann_graph_info
+ *              (n, M, 2M, max level, entry point, number of upper lists)
+ *              and ann_graph_export (the layout of ann_index_desc), free it
+ *              with ann_graph_free.
+ * Synchronizes `stream` (NULL: the null stream).  Allocates its device
+ * arrays (graph, per-node visited bitsets of the largest batch) and frees
+ * them before returning.
+ */
+typedef struct ann_graph ann_graph;
+int ann_hnsw_build(const float* X, int64_t n, int32_t d, int32_t metric, int32_t M, int32_t efc,
+                   const double* u, int64_t seq_prefix, double batch_frac, int64_t batch_cap,
+                   ann_graph** out, void* stream);
+int ann_graph_info(const ann_graph* g, int64_t* info);
+int ann_graph_export(const ann_graph* g, uint8_t* levels, int32_t* adj0, int32_t* upper_off,
+                     int32_t* upper_adj);
+int ann_graph_free(ann_graph* g);
+
 /* ---- product quantization on the device -------------------------------- */
 
 /*

@@ -92,6 +92,10 @@ SIGNATURES = {
     "ann_bruteforce": ([P, P, I64, I32, P, P, P, P], C.c_int),
     "ann_pq_train": ([P, I64, I32, P, I64, P, I32, I32, I32, P, P, P], C.c_int),
     "ann_pq_encode": ([P, I64, I32, P, I32, I32, P, P], C.c_int),
+    "ann_hnsw_build": ([P, I64, I32, I32, I32, I32, P, I64, C.c_double, I64, P, P], C.c_int),
+    "ann_graph_info": ([P, P], C.c_int),
+    "ann_graph_export": ([P, P, P, P, P], C.c_int),
+    "ann_graph_free": ([P], C.c_int),
     "ann_server_create": ([P, P, P], C.c_int),
     "ann_server_submit": ([P, P], C.c_int),
     "ann_server_poll": ([P, P, I32], C.c_int),
@@ -363,6 +367,41 @@ def ann_bruteforce(index, queries, k, stream=None):
     _check(lib().ann_bruteforce(index.handle, _dptr(queries), nq, int(k), _dptr(ids), _dptr(dists),
                                 _dptr(cert), _stream_handle(stream)))
     return ids, dists, cert
+
+
+class BuiltGraph:
+    """A graph built on the device, in the index layout (host numpy arrays)."""
+
+    def __init__(self, n, M, M0, max_level, entry, levels, adj0, upper_off, upper_adj):
+        self.n, self.M, self.M0, self.max_level, self.entry = n, M, M0, max_level, entry
+        self.levels, self.adj0, self.upper_off, self.upper_adj = levels, adj0, upper_off, upper_adj
+
+
+def ann_hnsw_build(X, metric, M, efc, u_levels, seq_prefix=None, batch_frac=0.0, batch_cap=4096,
+                   stream=None):
+    """HNSW construction on the device over X (device f32[n, d]); u_levels:
+    host f64[n].  seq_prefix None means every node is inserted alone."""
+    n, d = X.shape
+    u = np.ascontiguousarray(u_levels, dtype=np.float64)
+    assert u.shape == (n,)
+    if seq_prefix is None:
+        seq_prefix = n
+    g = C.c_void_p()
+    _check(lib().ann_hnsw_build(_dptr(X), n, d, METRIC[metric], int(M), int(efc), _hptr(u),
+                                int(seq_prefix), float(batch_frac), int(batch_cap), C.byref(g),
+                                _stream_handle(stream)))
+    try:
+        info = np.zeros(6, np.int64)
+        _check(lib().ann_graph_info(g, _hptr(info)))
+        n_, M_, M0, max_level, entry, nlists = (int(v) for v in info)
+        levels = np.empty(n_, np.uint8)
+        adj0 = np.empty((n_, M0), np.int32)
+        uoff = np.empty(n_, np.int32)
+        uadj = np.empty((nlists, M_), np.int32)
+        _check(lib().ann_graph_export(g, _hptr(levels), _hptr(adj0), _hptr(uoff), _hptr(uadj)))
+    finally:
+        lib().ann_graph_free(g)
+    return BuiltGraph(n_, M_, M0, max_level, entry, levels, adj0, uoff, uadj)
 
 
 def ann_pq_train(X, sample, init, m, ksub=256, max_iter=25, stream=None):
