@@ -161,3 +161,22 @@ def test_pq_training_and_encoding_at_full_size(big):
     torch.cuda.synchronize()
     say(f"encoded in {time.perf_counter() - t:.3f} s")
     assert np.array_equal(codes.cpu().numpy(), big["codes"])
+
+
+def test_graph_build_at_full_size(big):
+    """HNSW construction of the 1M x 768 set on the device (M=32, efC=200,
+    2,000 nodes one at a time, then batches of 2% up to 2,048) equals the
+    oracle's stored graph: levels, every list in order, entry point."""
+    import time
+    X = torch.from_numpy(big["X"]).to("cuda:0")
+    u = synth.level_uniforms(0, big["X"].shape[0])
+    say("graph construction on the device, 1,000,000 x 768")
+    t = time.perf_counter()
+    g = ann.ann_hnsw_build(X, "ip", 32, 200, u, seq_prefix=2000, batch_frac=0.02, batch_cap=2048)
+    say(f"built in {time.perf_counter() - t:.1f} s")
+    ref = big["g"]
+    assert g.max_level == ref.max_level and g.entry == ref.entry
+    assert np.array_equal(g.levels, ref.levels)
+    assert np.array_equal(g.upper_off, ref.upper_off)
+    assert np.array_equal(g.upper_adj, ref.upper_adj)
+    assert np.array_equal(g.adj0, ref.adj0)
