@@ -110,3 +110,23 @@ def test_serving_mix_1m_x_96():
             assert np.array_equal(got[t]["dists"], ref["keys"][j, :kk])
     finally:
         ix.close()
+
+
+def test_graph_build_serving_mix_1m_x_96():
+    """HNSW construction on the device of the 1,000,000 x 96 L2 set (M=32,
+    efC=200, 2,000 nodes one at a time, then batches of 2% up to 2,048)
+    equals the oracle's stored graph list for list."""
+    g = load_graph("gmm10m_n1000000")
+    spec = synth.WORKLOADS["gmm10m"]
+    X = synth.dense_base(spec, n=1_000_000)
+    u = synth.level_uniforms(0, X.shape[0])
+    say("graph construction on the device, 1,000,000 x 96")
+    t = time.perf_counter()
+    b = ann.ann_hnsw_build(torch.from_numpy(X).to("cuda:0"), "l2", 32, 200, u, seq_prefix=2000,
+                           batch_frac=0.02, batch_cap=2048)
+    say(f"built in {time.perf_counter() - t:.1f} s")
+    assert b.max_level == g.max_level and b.entry == g.entry
+    assert np.array_equal(b.levels, g.levels)
+    assert np.array_equal(b.upper_off, g.upper_off)
+    assert np.array_equal(b.upper_adj, g.upper_adj)
+    assert np.array_equal(b.adj0, g.adj0)
