@@ -101,9 +101,14 @@ def _declare(L):
     L.or_pq_train.argtypes = [P, I32, P, I64, P, I32, I32, I32, P, P, I32]
     L.or_pq_train.restype = I32
     L.or_pq_encode.argtypes = [P, I64, I32, P, I32, I32, P, I32]
+    L.or_ivf_train.argtypes = [P, I32, P, I64, P, I32, I32, P, P, I32]
+    L.or_ivf_train.restype = I32
+    L.or_ivf_assign.argtypes = [P, I64, I32, P, I32, P, I32]
+    L.or_ivf_search.argtypes = [P, P, I64, P, I32, P, P, I32, I32, I32, P, I32, I32, P, P, P, P,
+                                P, P, I32, I32]
     for f in ("or_encode_fp8_rows", "or_keys_dense", "or_keys_sparse", "or_pq_luts",
               "or_bruteforce", "or_graph_info", "or_graph_export", "or_graph_free",
-              "or_hnsw_search", "or_pq_encode"):
+              "or_hnsw_search", "or_pq_encode", "or_ivf_assign", "or_ivf_search"):
         getattr(L, f).restype = None
 
 
@@ -410,6 +415,61 @@ def pq_encode(X, codebook, threads=None):
     codes = np.empty((n, m), np.uint8)
     lib().or_pq_encode(_ptr(X), n, d, _ptr(cb), m, ksub, _ptr(codes), nthreads(threads))
     return codes
+
+
+# --------------------------------------------------------------------------
+# IVF (inverted lists over a k-means coarse quantizer)
+# --------------------------------------------------------------------------
+
+def ivf_train(X, nlist, sample_ids, init, max_iter=25, threads=None):
+    """k-means over whole rows of X[sample_ids].  Returns (centroids f32[nlist,d], iters, objective)."""
+    X = _c(X, np.float32); n, d = X.shape
+    s = _c(sample_ids, np.int64); ini = _c(init, np.int64)
+    assert ini.size == nlist and ini.max() < s.size
+    cent = np.empty((nlist, d), np.float32)
+    obj = np.zeros(max_iter, np.float64)
+    it = lib().or_ivf_train(_ptr(X), d, _ptr(s), s.size, _ptr(ini), nlist, max_iter, _ptr(cent),
+                            _ptr(obj), nthreads(threads))
+    return cent, int(it), obj
+
+
+def ivf_assign(X, centroids, threads=None):
+    """list[r] = EXACT nearest centroid of row r (lower index on ties), i32[n]."""
+    X = _c(X, np.float32); n, d = X.shape
+    cent = _c(centroids, np.float32)
+    out = np.empty(n, np.int32)
+    lib().or_ivf_assign(_ptr(X), n, d, _ptr(cent), cent.shape[0], _ptr(out), nthreads(threads))
+    return out
+
+
+def ivf_lists(assign, nlist):
+    """Inverted lists from an assignment: (list_off i64[nlist+1], list_ids i32[n]), ids ascending."""
+    a = np.asarray(assign, np.int64)
+    order = np.argsort(a, kind="stable").astype(np.int32)
+    off = np.zeros(nlist + 1, np.int64)
+    off[1:] = np.cumsum(np.bincount(a, minlength=nlist))
+    return off, order
+
+
+def ivf_search(store, centroids, list_off, list_ids, Q, k, nprobe, kmode="canon",
+               rerank_f32=None, rerank_depth=0, rerank_kmode="canon", w_cap=0, threads=None):
+    """IVF search (see or_ivf_search).  Returns dict(ids, keys, probes, stats[, w_ids, w_keys])."""
+    Q = _c(np.atleast_2d(Q), np.float32); nq = Q.shape[0]
+    cent = _c(centroids, np.float32); nlist = cent.shape[0]
+    off = _c(list_off, np.int64); lid = _c(list_ids, np.int32)
+    rr = _c(rerank_f32, np.float32) if rerank_f32 is not None else None
+    ids = np.empty((nq, k), np.int64); ks = np.empty((nq, k), np.float32)
+    probes = np.empty((nq, nprobe), np.int32); stats = np.empty((nq, 2), np.int64)
+    w_ids = np.empty((nq, w_cap), np.int32) if w_cap else None
+    w_keys = np.empty((nq, w_cap), np.float32) if w_cap else None
+    lib().or_ivf_search(store.ref, _ptr(Q), nq, _ptr(cent), nlist, _ptr(off), _ptr(lid), nprobe, k,
+                        KEYS[kmode], _ptr(rr), int(rerank_depth), KEYS[rerank_kmode], _ptr(ids),
+                        _ptr(ks), _ptr(probes), _ptr(stats), _ptr(w_ids), _ptr(w_keys), int(w_cap),
+                        nthreads(threads))
+    out = dict(ids=ids, keys=ks, probes=probes, stats=stats)
+    if w_cap:
+        out["w_ids"], out["w_keys"] = w_ids, w_keys
+    return out
 
 
 # --------------------------------------------------------------------------

@@ -17,7 +17,9 @@
 //  * Product Quantization (Section 2 and its citation: Jegou et al.), with
 //    asymmetric distances from per-query lookup tables;
 //  * the Identity quantizer (Section 2), plus reduced-precision storage
-//    copies (FP16, BF16, FP8-E4M3 with a per-vector scale).
+//    copies (FP16, BF16, FP8-E4M3 with a per-vector scale);
+//  * an inverted-file (IVF) index over a k-means coarse quantizer, the index
+//    family Section 1 names beside graphs and Section 5 plans to add.
 //
 // Distances are "keys", smaller is better: squared L2, or the negated inner
 // product.  Two evaluation modes exist:
@@ -595,7 +597,7 @@ int argmin_centroid(const float* x, const float* cb, int ksub, int ds, double* b
 
 extern "C" {
 
-int or_version() { return 3; }
+int or_version() { return 4; }
 
 void or_to_f16(const float* x, int64_t n, uint16_t* out) {
   for (int64_t i = 0; i < n; ++i) out[i] = f32_to_f16(x[i]);
@@ -866,17 +868,77 @@ void or_hnsw_search(const or_graph_in* gi, const or_store* s, const float* Q,
   }
 }
 
+// --- k-means (PQ per subspace, IVF coarse quantizer) -------------------------
+
+}  // extern "C"
+
+namespace {
+
+// Lloyd's k-means on ns points of ds dimensions (pts row-major).  Centroid j
+// starts at point init[j].  Each iteration assigns every point to its EXACT
+// nearest centroid (lower index on ties), stops when no assignment changed,
+// else replaces each centroid by the FP64 mean of its points (summed in
+// ascending point order, rounded once to FP32).  An empty cluster takes the
+// point of largest current error (lower position on ties) not already used
+// for re-seeding in this step, clusters in ascending order.  Runs at most
+// max_iter iterations; returns the number run.  obj[it] += the summed error
+// of iteration it's assignment.  `threads` splits the assignment over points
+// (it changes nothing but the rounding of obj).
+int lloyd(const float* pts, int64_t ns, int ds, const int64_t* init, int ksub, int max_iter,
+          float* C, double* obj, int threads) {
+  for (int j = 0; j < ksub; ++j)
+    for (int t = 0; t < ds; ++t) C[(size_t)j * ds + t] = pts[(size_t)init[j] * ds + t];
+  std::vector<int> asg((size_t)ns, -1);
+  std::vector<double> err((size_t)ns);
+  int it = 0;
+  for (; it < max_iter; ++it) {
+    int changed = 0;
+    double total = 0.0;
+#pragma omp parallel for schedule(static) num_threads(threads) if (threads > 1) reduction(| : changed) reduction(+ : total)
+    for (int64_t a = 0; a < ns; ++a) {
+      double e;
+      int j = argmin_centroid(&pts[(size_t)a * ds], C, ksub, ds, &e);
+      if (j != asg[a]) { changed = 1; asg[a] = j; }
+      err[a] = e; total += e;
+    }
+    obj[it] += total;
+    if (!changed) break;
+    std::vector<double> sum((size_t)ksub * ds, 0.0);
+    std::vector<int64_t> cnt((size_t)ksub, 0);
+    for (int64_t a = 0; a < ns; ++a) {
+      ++cnt[asg[a]];
+      for (int t = 0; t < ds; ++t) sum[(size_t)asg[a] * ds + t] += (double)pts[(size_t)a * ds + t];
+    }
+    std::vector<int64_t> order;   // point positions by decreasing error
+    size_t next = 0;
+    for (int j = 0; j < ksub; ++j) {
+      if (cnt[j] > 0) {
+        for (int t = 0; t < ds; ++t) C[(size_t)j * ds + t] = (float)(sum[(size_t)j * ds + t] / (double)cnt[j]);
+      } else {
+        if (order.empty()) {
+          order.resize((size_t)ns);
+          for (int64_t a = 0; a < ns; ++a) order[a] = a;
+          std::stable_sort(order.begin(), order.end(),
+                           [&](int64_t x, int64_t y) { return err[x] > err[y]; });
+        }
+        const int64_t pick = order[std::min(next++, order.size() - 1)];
+        for (int t = 0; t < ds; ++t) C[(size_t)j * ds + t] = pts[(size_t)pick * ds + t];
+      }
+    }
+  }
+  return it + (it < max_iter ? 1 : 0);
+}
+
+}  // namespace
+
+extern "C" {
+
 // --- PQ training and encoding ------------------------------------------------
 
-// k-means per subspace on the sample rows (ids into X).  init[j] indexes the
-// sample: centroid j starts at sample point init[j].  Lloyd iterations:
-// assign to the EXACT nearest centroid (lower index on ties), then each
-// centroid becomes the FP64 mean of its points rounded to FP32.  An empty
-// cluster is re-seeded with the sample point of largest current error (lower
-// sample position on ties) not already used for re-seeding in this step.
-// Stops after max_iter iterations or when no assignment changes.
-// Returns the iterations run; objective[it] receives the summed error of the
-// assignment made in iteration it (max_iter entries, may be NULL).
+// k-means (lloyd above) per subspace on the sample rows (ids into X); init[j]
+// indexes the sample.  Returns the largest iteration count of a subspace;
+// objective[it] receives the summed error of the assignment made in
+// iteration it (max_iter entries, may be NULL).
 int or_pq_train(const float* X, int d, const int64_t* sample, int64_t ns, const int64_t* init,
                 int m, int ksub, int max_iter, float* cb, double* objective, int threads) {
   const int ds = d / m;
@@ -887,48 +949,12 @@ int or_pq_train(const float* X, int d, const int64_t* sample, int64_t ns, const 
     std::vector<float> pts((size_t)ns * ds);
     for (int64_t a = 0; a < ns; ++a)
       for (int t = 0; t < ds; ++t) pts[(size_t)a * ds + t] = X[(size_t)sample[a] * d + sub * ds + t];
-    float* C = cb + (size_t)sub * ksub * ds;
-    for (int j = 0; j < ksub; ++j)
-      for (int t = 0; t < ds; ++t) C[(size_t)j * ds + t] = pts[(size_t)init[j] * ds + t];
-    std::vector<int> asg((size_t)ns, -1);
-    std::vector<double> err((size_t)ns);
-    int it = 0;
-    for (; it < max_iter; ++it) {
-      bool changed = false;
-      double total = 0.0;
-      for (int64_t a = 0; a < ns; ++a) {
-        double e;
-        int j = argmin_centroid(&pts[(size_t)a * ds], C, ksub, ds, &e);
-        if (j != asg[a]) { changed = true; asg[a] = j; }
-        err[a] = e; total += e;
-      }
+    std::vector<double> obj((size_t)max_iter, 0.0);
+    const int it = lloyd(pts.data(), ns, ds, init, ksub, max_iter, cb + (size_t)sub * ksub * ds,
+                         obj.data(), 1);
 #pragma omp critical
-      obj_sum[it] += total;
-      if (!changed) break;
-      std::vector<double> sum((size_t)ksub * ds, 0.0);
-      std::vector<int64_t> cnt((size_t)ksub, 0);
-      for (int64_t a = 0; a < ns; ++a) {
-        ++cnt[asg[a]];
-        for (int t = 0; t < ds; ++t) sum[(size_t)asg[a] * ds + t] += (double)pts[(size_t)a * ds + t];
-      }
-      std::vector<int64_t> order;   // sample positions by decreasing error
-      size_t next = 0;
-      for (int j = 0; j < ksub; ++j) {
-        if (cnt[j] > 0) {
-          for (int t = 0; t < ds; ++t) C[(size_t)j * ds + t] = (float)(sum[(size_t)j * ds + t] / (double)cnt[j]);
-        } else {
-          if (order.empty()) {
-            order.resize((size_t)ns);
-            for (int64_t a = 0; a < ns; ++a) order[a] = a;
-            std::stable_sort(order.begin(), order.end(),
-                             [&](int64_t x, int64_t y) { return err[x] > err[y]; });
-          }
-          const int64_t pick = order[std::min(next++, order.size() - 1)];
-          for (int t = 0; t < ds; ++t) C[(size_t)j * ds + t] = pts[(size_t)pick * ds + t];
-        }
-      }
-    }
-    iters_run = std::max(iters_run, it + (it < max_iter ? 1 : 0));
+    for (int t = 0; t < max_iter; ++t) obj_sum[t] += obj[t];
+    iters_run = std::max(iters_run, it);
   }
   if (objective)
     for (int it = 0; it < max_iter; ++it) objective[it] = obj_sum[it];
@@ -944,6 +970,94 @@ void or_pq_encode(const float* X, int64_t n, int d, const float* cb, int m, int 
     for (int sub = 0; sub < m; ++sub)
       codes[(size_t)r * m + sub] = (uint8_t)argmin_centroid(
           X + (size_t)r * d + sub * ds, cb + (size_t)sub * ksub * ds, ksub, ds, nullptr);
+}
+
+
+// --- IVF: inverted lists over a coarse quantizer ------------------------------
+//
+// The paper names IVF (Section 1) as one of the index families an ANN library
+// offers, and plans more index types (Section 5).  The coarse quantizer is
+// k-means over the whole vector (lloyd above on a sample, L2), every row
+// belongs to the list of its EXACT nearest centroid, and a query scans the
+// lists of its nprobe nearest centroids.
+
+// Coarse centroids: lloyd on the sample rows of X; init[j] indexes the sample.
+int or_ivf_train(const float* X, int d, const int64_t* sample, int64_t ns, const int64_t* init,
+                 int nlist, int max_iter, float* cent, double* objective, int threads) {
+  std::vector<float> pts((size_t)ns * d);
+  for (int64_t a = 0; a < ns; ++a)
+    std::memcpy(&pts[(size_t)a * d], X + (size_t)sample[a] * d, sizeof(float) * d);
+  std::vector<double> obj((size_t)max_iter, 0.0);
+  const int it = lloyd(pts.data(), ns, d, init, nlist, max_iter, cent, obj.data(), threads);
+  if (objective)
+    for (int t = 0; t < max_iter; ++t) objective[t] = obj[t];
+  return it;
+}
+
+// list[r] = EXACT nearest centroid of row r (lower index on ties).
+void or_ivf_assign(const float* X, int64_t n, int d, const float* cent, int nlist, int32_t* list,
+                   int threads) {
+#pragma omp parallel for schedule(static) num_threads(threads)
+  for (int64_t r = 0; r < n; ++r) list[r] = argmin_centroid(X + (size_t)r * d, cent, nlist, d, nullptr);
+}
+
+// IVF search.  For query i:
+//  * probe keys: squared L2 from the FP32 query to every FP32 centroid, in
+//    `kmode` (CANON: the FP32 fixed order of a dense FP32 row);
+//  * probes: the min(nprobe, nlist) smallest (key, list id);
+//  * candidates: every row of the probed lists, keyed in `kmode` on the
+//    store's representation with the index metric, sorted by (key, id);
+//  * with rerank_depth R > 0 the first min(max(R, k), #candidates) are
+//    re-keyed on the FP32 rows (rerank_kmode) and re-sorted;
+//  * out_ids/out_keys [nq][k]: the first k, -1 / +inf padded.
+// out_probes [nq][nprobe] (-1 padded), stats [nq][2] = distance evaluations
+// (candidates) and lists probed, w_ids/w_keys [nq][w_cap] the first w_cap
+// sorted candidates before the rerank; each may be NULL.
+void or_ivf_search(const or_store* s, const float* Q, int64_t nq, const float* cent, int nlist,
+                   const int64_t* list_off, const int32_t* list_ids, int nprobe, int k, int kmode,
+                   const float* rerank_f32, int rerank_depth, int rerank_kmode, int64_t* out_ids,
+                   float* out_keys, int32_t* out_probes, int64_t* stats, int32_t* w_ids,
+                   float* w_keys, int w_cap, int threads) {
+  Store st = to_store(s);
+  Store cs; cs.mode = MODE_F32; cs.metric = MET_L2; cs.d = st.d; cs.f32 = cent;
+  const int np = std::min(nprobe, nlist);
+#pragma omp parallel for schedule(dynamic, 1) num_threads(std::max(1, threads))
+  for (int64_t i = 0; i < nq; ++i) {
+    const float* q = Q + (size_t)i * st.d;
+    std::vector<KI> pk((size_t)nlist);
+    for (int j = 0; j < nlist; ++j) pk[j] = KI{dense_key(cs, q, j, kmode), j};
+    std::sort(pk.begin(), pk.end(), lt);
+    Evaluator ev(&st, kmode);
+    ev.bind_dense(q);
+    std::vector<KI> cand;
+    for (int p = 0; p < np; ++p) {
+      const int l = pk[p].id;
+      for (int64_t t = list_off[l]; t < list_off[l + 1]; ++t)
+        cand.push_back(KI{ev.key(list_ids[t]), list_ids[t]});
+    }
+    std::sort(cand.begin(), cand.end(), lt);
+    std::vector<KI> res = cand;
+    if (rerank_f32 && rerank_depth > 0) {
+      Store orig; orig.mode = MODE_F32; orig.metric = st.metric; orig.d = st.d; orig.f32 = rerank_f32;
+      const int R = (int)std::min<int64_t>((int64_t)cand.size(), std::max(rerank_depth, k));
+      res.resize(R);
+      for (int j = 0; j < R; ++j) res[j].k = dense_key(orig, q, cand[j].id, rerank_kmode);
+      std::sort(res.begin(), res.end(), lt);
+    }
+    for (int j = 0; j < k; ++j) {
+      const bool ok = j < (int)res.size();
+      out_ids[i * k + j] = ok ? res[j].id : -1;
+      out_keys[i * k + j] = ok ? res[j].k : INFINITY;
+    }
+    if (out_probes)
+      for (int p = 0; p < nprobe; ++p) out_probes[i * nprobe + p] = p < np ? pk[p].id : -1;
+    if (stats) { stats[i * 2 + 0] = (int64_t)cand.size(); stats[i * 2 + 1] = np; }
+    if (w_ids)
+      for (int j = 0; j < w_cap; ++j) {
+        w_ids[i * w_cap + j] = j < (int)cand.size() ? cand[j].id : -1;
+        w_keys[i * w_cap + j] = j < (int)cand.size() ? cand[j].k : INFINITY;
+      }
+  }
 }
 
 }  // extern "C"

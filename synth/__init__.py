@@ -11,7 +11,8 @@ The paper evaluates on SIFT1M (dense, L2, 128-d), MS MARCO passage embeddings
 generators below produce stand-ins with the same shapes and measures.
 
 Every workload takes one integer seed.  ``SeedSequence(seed)`` is split into
-six named child streams (centres, base, queries, levels, pq_sample, arrivals),
+named child streams (centres, base, queries, levels, pq_sample, arrivals,
+ivf_sample),
 so that for instance the number of queries never changes the base set.  Large
 arrays are drawn in chunks of ``CHUNK`` rows, each chunk from its own
 grandchild stream, which makes generation order-independent and parallel.
@@ -26,7 +27,7 @@ from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
-STREAMS = ("centres", "base", "queries", "levels", "pq_sample", "arrivals")
+STREAMS = ("centres", "base", "queries", "levels", "pq_sample", "arrivals", "ivf_sample")
 CHUNK = 65536
 
 
@@ -225,6 +226,16 @@ def pq_sample(seed, n, n_sample, n_centroids):
     rng = np.random.default_rng(stream(seed, "pq_sample"))
     ids = np.sort(rng.choice(n, size=min(n, n_sample), replace=False)).astype(np.int64)
     init = rng.permutation(ids.size)[:n_centroids].astype(np.int64)
+    return ids, init
+
+
+def ivf_sample(seed, n, n_sample, nlist):
+    """Coarse-quantizer training sample ids (without replacement, ascending)
+    and the k-means init order (indexes into the sample), like pq_sample but
+    from a stream of its own."""
+    rng = np.random.default_rng(stream(seed, "ivf_sample"))
+    ids = np.sort(rng.choice(n, size=min(n, n_sample), replace=False)).astype(np.int64)
+    init = rng.permutation(ids.size)[:nlist].astype(np.int64)
     return ids, init
 
 
