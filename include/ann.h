@@ -368,6 +368,67 @@ int ann_pq_train(const float* X, int64_t n, int32_t d, const int64_t* sample, in
 int ann_pq_encode(const float* X, int64_t n, int32_t d, const float* codebook, int32_t m,
                   int32_t ksub, uint8_t* out_codes, void* stream);
 
+/* ---- IVF index (inverted lists over a coarse quantizer) ------------------ */
+
+/*
+ * An inverted-file index, the index family the paper names beside graphs
+ * (Section 1) and plans to add (Section 5).  The coarse quantizer is a set of
+ * nlist FP32 centroids (k-means over whole vectors, e.g. ann_pq_train with
+ * m = 1 or the oracle's training); list l holds the rows whose nearest
+ * centroid is l.  The IVF index searches the rows (or PQ codes) of an
+ * existing ann_index, which must outlive it; it adds only the centroids and
+ * the lists to device memory.
+ *
+ * ann_ivf_create (host arrays, copied; the caller may free them afterwards):
+ *   centroids  f32[nlist][d], finite; 1 <= nlist <= 8192, d a multiple of 4
+ *              and at most 1024
+ *   list_off   i64[nlist + 1], list_off[0] = 0, non-decreasing, list_off[nlist] = n
+ *   list_ids   i32[n]: list l is list_ids[list_off[l] .. list_off[l+1]); every
+ *              row 0..n-1 exactly once (any order inside a list)
+ * ANN_EFORMAT when the lists are not a partition of the rows.
+ *
+ * ann_ivf_search: for each query, the probe keys are the squared L2 distances
+ * from the FP32 query to the centroids, in the fixed FP32 order of a dense
+ * FP32 row; the lists of the min(nprobe, nlist) smallest (key, list id) are
+ * scanned; each of their rows is keyed like the HNSW search keys it in
+ * `mode` (the index metric); the candidates are ordered by (key, id).  With
+ * rerank R > 0 the first min(max(R, k), #candidates) are re-keyed on the
+ * FP32 rows and re-sorted.  The first k are returned.
+ *   mode         ANN_MODE_F32 / F16 / BF16 / FP8 / PQ (not SPARSE)
+ *   rerank       0 .. ANN_K_MAX (needs x_f32 when > 0)
+ *   queries      device f32[nq][d]
+ *   k            1 .. ANN_K_MAX;  nprobe >= 1 (values above nlist scan all)
+ *   out_ids      device i64[nq][k], ascending (key, id), -1 padded when the
+ *                probed lists hold fewer than k rows
+ *   out_dists    device f32[nq][k], +inf with id -1
+ *   out_probes   optional device i32[nq][nprobe]: the probed lists in probe
+ *                order, -1 beyond nlist
+ *   out_stats    optional device i32[nq][2]: distance evaluations (rows
+ *                scanned), lists probed
+ * Asynchronous on `stream` (NULL: the index's stream, and the call waits).
+ * Without out_probes the probe lists go to a scratch buffer the IVF object
+ * owns (4 bytes per query and probe, grown on demand); batches on different
+ * streams are ordered on it by an event.
+ */
+typedef struct ann_ivf ann_ivf;
+typedef struct ann_ivf_batch {
+  int32_t mode;
+  int32_t rerank;
+  int64_t nq;
+  const float* queries;
+  int32_t k;
+  int32_t nprobe;
+  int64_t* out_ids;
+  float* out_dists;
+  int32_t* out_probes;
+  int32_t* out_stats;
+} ann_ivf_batch;
+
+int ann_ivf_create(ann_index* ix, int32_t nlist, const float* centroids, const int64_t* list_off,
+                   const int32_t* list_ids, ann_ivf** out);
+int ann_ivf_free(ann_ivf* v);
+int ann_ivf_search(ann_ivf* v, const ann_ivf_batch* b, void* stream);
+
 /* ---- serving: continuous batching ------------------------------------------ */
 
 typedef struct ann_server ann_server;

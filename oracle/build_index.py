@@ -11,6 +11,8 @@ Files go to ``data/<workload>[_n<N>]/`` at the repository root:
   gt.npz         exact top-100 ids/keys of the queries (EXACT keys, (key, id) order)
   pq.npz         PQ codebook f32[m,256,dsub] and codes u8[n,m]
   fp8.npz        per-row scaled E4M3 codes and scales
+  ivf.npz        IVF coarse centroids f32[nlist,d] and inverted lists
+                 (list_off i64[nlist+1], list_ids i32[n])
 The base vectors and queries are not stored: ``synth`` regenerates them.
 """
 from __future__ import annotations
@@ -28,6 +30,10 @@ if ROOT not in sys.path:
 
 import oracle  # noqa: E402
 import synth  # noqa: E402
+
+# IVF coarse quantizer: lists and training-sample size per workload.
+IVF_NLIST = 1024
+IVF_SAMPLE = 100_000
 
 # Batched insertion keeps the searches of one batch against a frozen graph;
 # the first SEQ_PREFIX nodes go in one at a time.
@@ -185,6 +191,18 @@ def main(argv=None):
         codes, scale = oracle.encode_fp8_rows(X, threads=a.threads)
         np.savez(os.path.join(out, "fp8.npz"), codes=codes, scale=scale)
         log("fp8 copy written")
+    if "ivf" in what:
+        if X is None:
+            X = synth.dense_base(spec, n=n)
+        nlist = min(IVF_NLIST, n)
+        sample, init = synth.ivf_sample(0, n, IVF_SAMPLE, nlist)
+        t = time.time()
+        cent, iters, obj = oracle.ivf_train(X, nlist, sample, init, 25, threads=a.threads)
+        log(f"ivf trained ({iters} iterations) in {time.time() - t:.1f}s")
+        off, ids = oracle.ivf_lists(oracle.ivf_assign(X, cent, threads=a.threads), nlist)
+        np.savez(os.path.join(out, "ivf.npz"), centroids=cent, list_off=off, list_ids=ids,
+                 objective=obj, iters=iters)
+        log(f"ivf lists written in {time.time() - t:.1f}s (sizes {np.diff(off).min()}..{np.diff(off).max()})")
 
 
 if __name__ == "__main__":

@@ -79,6 +79,12 @@ class AnnCompletion(C.Structure):
 
 # Every exported symbol and its argument types; the CPU tests check that the
 # library exports all of them.
+class AnnIvfBatch(C.Structure):
+    _fields_ = [("mode", I32), ("rerank", I32), ("nq", I64), ("queries", P), ("k", I32),
+                ("nprobe", I32), ("out_ids", P), ("out_dists", P), ("out_probes", P),
+                ("out_stats", P)]
+
+
 SIGNATURES = {
     "ann_index_create": ([P, C.c_int, P], C.c_int),
     "ann_index_free": ([P], C.c_int),
@@ -96,6 +102,9 @@ SIGNATURES = {
     "ann_graph_info": ([P, P], C.c_int),
     "ann_graph_export": ([P, P, P, P, P], C.c_int),
     "ann_graph_free": ([P], C.c_int),
+    "ann_ivf_create": ([P, I32, P, P, P, P], C.c_int),
+    "ann_ivf_free": ([P], C.c_int),
+    "ann_ivf_search": ([P, P, P], C.c_int),
     "ann_server_create": ([P, P, P], C.c_int),
     "ann_server_submit": ([P, P], C.c_int),
     "ann_server_poll": ([P, P, I32], C.c_int),
@@ -432,6 +441,69 @@ def ann_pq_encode(X, codebook, stream=None):
 # --------------------------------------------------------------------------
 # serving
 # --------------------------------------------------------------------------
+
+# --------------------------------------------------------------------------
+# IVF index
+# --------------------------------------------------------------------------
+
+class Ivf:
+    """Owns an ann_ivf handle (inverted lists over an Index, which it keeps alive)."""
+
+    def __init__(self, handle, index, nlist):
+        self.handle, self.index, self.nlist = handle, index, nlist
+
+    def close(self):
+        if self.handle:
+            lib().ann_ivf_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ann_ivf_create(index, centroids, list_off, list_ids):
+    """Host arrays: centroids f32[nlist, d], list_off i64[nlist+1], list_ids i32[n]."""
+    cent = _np(centroids, np.float32)
+    off = _np(list_off, np.int64)
+    ids = _np(list_ids, np.int32)
+    h = P()
+    _check(lib().ann_ivf_create(index.handle, int(cent.shape[0]), _hptr(cent), _hptr(off),
+                                _hptr(ids), C.byref(h)))
+    return Ivf(h, index, int(cent.shape[0]))
+
+
+def ann_ivf_free(ivf):
+    ivf.close()
+
+
+def ann_ivf_search(ivf, queries, k, nprobe, mode="f32", rerank=0, want_probes=False,
+                   want_stats=False, stream=None, out=None):
+    """IVF search of cuda float32 queries [nq, d].  Returns a dict of tensors
+    (ids, dists[, probes][, stats]).  Blocking unless a stream is given."""
+    torch = _torch()
+    nq = queries.shape[0]
+    dev = queries.device
+    res = out or {}
+    if "ids" not in res:
+        res["ids"] = torch.empty((nq, k), dtype=torch.int64, device=dev)
+        res["dists"] = torch.empty((nq, k), dtype=torch.float32, device=dev)
+        if want_probes:
+            res["probes"] = torch.empty((nq, nprobe), dtype=torch.int32, device=dev)
+        if want_stats:
+            res["stats"] = torch.empty((nq, 2), dtype=torch.int32, device=dev)
+    b = AnnIvfBatch()
+    b.mode = MODE[mode] if isinstance(mode, str) else int(mode)
+    b.rerank, b.nq, b.queries = int(rerank), nq, _dptr(queries)
+    b.k, b.nprobe = int(k), int(nprobe)
+    b.out_ids, b.out_dists = _dptr(res["ids"]), _dptr(res["dists"])
+    b.out_probes = _dptr(res.get("probes"))
+    b.out_stats = _dptr(res.get("stats"))
+    _check(lib().ann_ivf_search(ivf.handle, C.byref(b), _stream_handle(stream)))
+    return res
+
 
 class Server:
     """Continuous-batching server around ann_server_* (host query vectors)."""

@@ -33,7 +33,7 @@ def test_struct_layouts_match_the_c_header(tmp_path):
     structs = {"ann_index_desc": ann.AnnIndexDesc, "ann_batch": ann.AnnBatch,
                "ann_launch_cfg": ann.AnnLaunchCfg, "ann_index_info": ann.AnnIndexInfo,
                "ann_server_cfg": ann.AnnServerCfg, "ann_request": ann.AnnRequest,
-               "ann_completion": ann.AnnCompletion}
+               "ann_completion": ann.AnnCompletion, "ann_ivf_batch": ann.AnnIvfBatch}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ann.h"', 'int main(void) {']
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
@@ -59,6 +59,9 @@ def test_null_arguments_rejected():
     assert L.ann_search(None, None, 0, 10, 10, None, None) == ann.ANN_EINVAL
     assert L.ann_search_ex(None, None, None) == ann.ANN_EINVAL
     assert L.ann_index_free(None) == ann.ANN_OK
+    assert L.ann_ivf_create(None, 4, None, None, None, C.byref(out)) == ann.ANN_EINVAL
+    assert L.ann_ivf_search(None, None, None) == ann.ANN_EINVAL
+    assert L.ann_ivf_free(None) == ann.ANN_OK
 
 
 def test_pq_arguments_checked_on_the_host():
