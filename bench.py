@@ -19,7 +19,10 @@ The same search with FP32 rows (no rerank) is timed beside it.
 Prints ONE JSON line with QPS, ms per step, recall@10, p50/p99 latency under
 Poisson arrivals (continuous-batching server), the roofline of the search
 kernel (algorithmic bytes / kernel time, HIP events on the launch stream)
-and the oracle's CPU throughput on a bounded sample.
+and the oracle's CPU throughput on a bounded sample.  Beside the headline it
+reports the exact scan on matrix cores and the IVF index over the same rows
+(oracle-built lists, the smallest nprobe reaching recall@10 0.95 in
+profiles/<workload>_ivf_sweep.json).
 """
 from __future__ import annotations
 
@@ -108,6 +111,50 @@ def algorithmic_bytes(stats, mode, d, M0, k, rerank):
     return int(per_q.sum())
 
 
+def ivf_bytes(stats, mode, d, k, rerank, nlist):
+    """Bytes an IVF search must read/write per launch: the centroids (probe
+    keys), every scanned row and its id, the list offsets, the rerank rows,
+    the query and the output."""
+    evals = stats[:, 0].astype(np.int64)
+    lists = stats[:, 1].astype(np.int64)
+    rr = np.minimum(max(rerank, k), evals) if rerank else np.zeros_like(evals)
+    per_q = (nlist * d * 4 + evals * (row_bytes(mode, d) + 4) + lists * 16 + rr * d * 4
+             + d * 4 + k * 12)
+    return int(per_q.sum())
+
+
+def load_ivf(name):
+    p = os.path.join(ROOT, "data", name, "ivf.npz")
+    return np.load(p) if os.path.exists(p) else None
+
+
+def pick_nprobe(sweep, mode_key, target=0.95):
+    if not sweep or mode_key not in sweep:
+        return None, None
+    pts = sorted(sweep[mode_key], key=lambda r: r["nprobe"])
+    for r in pts:
+        if r["recall"] >= target:
+            return r["nprobe"], r["recall"]
+    return pts[-1]["nprobe"], pts[-1]["recall"]
+
+
+class IvfTimed:
+    """One IVF search configuration: K steps bracketed by events on the stream."""
+
+    def __init__(self, ann, torch, ivf, mode, Q, k, nprobe, rerank, stream):
+        self.ann, self.torch, self.ivf = ann, torch, ivf
+        self.mode, self.Q, self.k, self.nprobe, self.rerank = mode, Q, k, nprobe, rerank
+        self.stream = stream
+        self.out = None
+
+    def step(self):
+        self.out = self.ann.ann_ivf_search(self.ivf, self.Q, self.k, self.nprobe, mode=self.mode,
+                                           rerank=self.rerank, want_stats=True,
+                                           stream=self.stream, out=self.out)
+        return self.out
+
+
+
 def sweep_ef(name):
     p = os.path.join(PROFILES, f"{name}_ef_sweep.json")
     if os.path.exists(p):
@@ -156,6 +203,21 @@ class Timed:
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         return e0.elapsed_time(e1) / steps, wall
+
+
+IvfTimed.run = Timed.run
+
+
+def ivf_row(ann, torch, ivf, mode, Qd, k, nprobe, rerank, stream, gt, d, nlist, steps, warmup):
+    tm = IvfTimed(ann, torch, ivf, mode, Qd, k, nprobe, rerank, stream)
+    ms, _ = tm.run(steps, warmup)
+    nq = Qd.shape[0]
+    rec = recall(tm.out["ids"].cpu().numpy(), gt, k) if gt is not None else None
+    nb = ivf_bytes(tm.out["stats"].cpu().numpy(), mode, d, k, rerank, nlist)
+    gbs = nb / (ms / 1e3) / 1e9
+    return {"nprobe": nprobe, "qps": round(nq / (ms / 1e3), 1), "recall@10": rec,
+            "ms_per_step": round(ms, 3), "algorithmic_GBps": round(gbs, 1),
+            "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": nb}
 
 
 def serve_latency(ann, ix, Q, k, ef, mode, rerank, qps_peak, seconds=3.0, seed=0):
@@ -258,6 +320,11 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="copy BYTES between two device buffers 3 times and exit (the plain "
                          "copy that scales the HBM traffic counters)")
+    ap.add_argument("--ivf-sweep", default=None, help="comma-separated nprobe values: write the "
+                    "IVF sweep file (profiles/<workload>_ivf_sweep.json)")
+    ap.add_argument("--ivf-only", action="store_true",
+                    help="time only the IVF search at its chosen nprobe (for profiling)")
+    ap.add_argument("--no-ivf", action="store_true")
     ap.add_argument("--sweep", default=None, help="comma-separated ef values: write the sweep file")
     ap.add_argument("--sweep-out", default=None, help="where the sweep JSON goes "
                     "(default profiles/<workload>_ef_sweep.json)")
@@ -290,6 +357,38 @@ def main():
     dev = "cuda:0"
     Qd = torch.from_numpy(Q).to(dev)
     stream = torch.cuda.Stream()
+
+    ivf_data = load_ivf(a.workload)
+    ivf = None
+    if ivf_data is not None and not a.no_ivf:
+        ivf = ann.ann_ivf_create(ix, ivf_data["centroids"], ivf_data["list_off"], ivf_data["list_ids"])
+        nlist = int(ivf_data["centroids"].shape[0])
+    if a.ivf_sweep:
+        res = {}
+        for key, mode, rr in (("f16+rerank", "f16", a.rerank), ("f32", "f32", 0)):
+            pts = []
+            for npb in (int(v) for v in a.ivf_sweep.split(",")):
+                row = ivf_row(ann, torch, ivf, mode, Qd, k, npb, rr, stream, gt, d, nlist, 1, 1)
+                pts.append({"nprobe": npb, "recall": row["recall@10"], "qps": row["qps"],
+                            "algorithmic_GBps": row["algorithmic_GBps"]})
+                log(f"ivf sweep {key} nprobe={npb} recall@10={row['recall@10']:.4f} "
+                    f"qps={row['qps']:.0f} {row['algorithmic_GBps']:.0f} GB/s")
+            res[key] = pts
+        path = os.path.join(PROFILES, f"{a.workload}_ivf_sweep.json")
+        with open(path, "w") as f:
+            json.dump({"workload": a.workload, "k": k, "rerank": a.rerank, "nlist": nlist, **res}, f,
+                      indent=1)
+        return
+    ivf_sweep = None
+    p_sw = os.path.join(PROFILES, f"{a.workload}_ivf_sweep.json")
+    if os.path.exists(p_sw):
+        ivf_sweep = json.load(open(p_sw))
+    if a.ivf_only:
+        npb, _ = pick_nprobe(ivf_sweep, "f16+rerank")
+        row = ivf_row(ann, torch, ivf, a.mode, Qd, k, npb or 64, a.rerank, stream, gt, d, nlist,
+                      a.steps, a.warmup)
+        print(json.dumps({"ivf": row, "mode": a.mode, "rerank": a.rerank}), flush=True)
+        return
 
     if a.sweep:
         res = {}
@@ -383,6 +482,29 @@ def main():
     except ann.AnnError as e:
         log(f"bruteforce skipped: {e}")
 
+    # IVF index over the same rows (an index family beside the graph)
+    ivf_rows = None
+    if ivf is not None:
+        ivf_rows = {"nlist": nlist}
+        for key, mode, rr in (("f16+rerank", a.mode, a.rerank), ("f32", "f32", 0)):
+            npb, _ = pick_nprobe(ivf_sweep, key)
+            if npb is None:
+                continue
+            ivf_rows[key] = ivf_row(ann, torch, ivf, mode, Qd, k, npb, rr, stream, gt, d, nlist,
+                                    a.steps, a.warmup)
+            tp = os.path.join(PROFILES, f"ivf_{a.workload}_traffic.json")
+            if os.path.exists(tp):
+                t = json.load(open(tp))
+                if (t.get("nprobe") == npb and t.get("mode") == mode and t.get("rerank") == rr
+                        and t.get("kernel_sha") == ivf_sha()):
+                    ivf_rows[key]["traffic"] = t.get("bytes_per_launch")
+            log(f"ivf {key} nprobe={npb}: {ivf_rows[key]['qps']:.0f} QPS, recall "
+                f"{ivf_rows[key]['recall@10']}, {ivf_rows[key]['algorithmic_GBps']:.0f} GB/s")
+        if ivf_sweep:
+            ivf_rows["nprobe_sweep"] = {k_: [[r["nprobe"], round(r["recall"], 4), round(r["qps"], 1)]
+                                             for r in v] for k_, v in ivf_sweep.items()
+                                        if isinstance(v, list)}
+
     p50 = p99 = rate = None
     p50_32 = p99_32 = rate32 = None
     if not a.no_serve:
@@ -439,6 +561,7 @@ def main():
             "cpu_oracle_single_thread": cpu1,
             "wall_s": round(wall, 3),
             "bruteforce_mfma": bf,
+            "ivf": ivf_rows,
         },
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -446,6 +569,8 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    if ivf is not None:
+        ivf.close()
     ix.close()
 
 
@@ -471,15 +596,21 @@ def build_bench(ann, torch, spec, g, X):
                       "equal_to_stored_graph": same}), flush=True)
 
 
-def kernel_sha():
-    """Hash of the search kernels' sources (the traffic counters describe one version)."""
+def kernel_sha(pattern="search_*"):
+    """Hash of the kernels' sources (the traffic counters describe one version)."""
     import glob
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2501_06121_amd", "csrc")
-    for p in sorted(glob.glob(os.path.join(csrc, "search_*"))):
+    for p in sorted(glob.glob(os.path.join(csrc, pattern))):
         h.update(open(p, "rb").read())
     return h.hexdigest()[:16]
+
+
+def ivf_sha():
+    """The IVF scan compiles the search's scoring policies (search_impl.h) into ivf.hip."""
+    import hashlib
+    return hashlib.sha256((kernel_sha("ivf.hip") + kernel_sha("search_impl.h")).encode()).hexdigest()[:16]
 
 
 if __name__ == "__main__":

@@ -180,3 +180,52 @@ def test_graph_build_at_full_size(big):
     assert np.array_equal(g.upper_off, ref.upper_off)
     assert np.array_equal(g.upper_adj, ref.upper_adj)
     assert np.array_equal(g.adj0, ref.adj0)
+
+
+def ivf_nprobe():
+    import json
+    p = os.path.join(ROOT, "profiles", "vmf1m_ivf_sweep.json")
+    if not os.path.exists(p):
+        return 64, 64
+    s = json.load(open(p))
+
+    def pick(key):
+        pts = sorted(s[key], key=lambda r: r["nprobe"])
+        for r in pts:
+            if r["recall"] >= 0.95:
+                return r["nprobe"]
+        return pts[-1]["nprobe"]
+    return pick("f16+rerank"), pick("f32")
+
+
+@pytest.mark.parametrize("mode", ["f16", "f32"])
+def test_ivf_full_batch_sampled_bitexact(big, mode):
+    """IVF over the oracle's 1,024 lists: all 10,000 queries in one launch at the
+    benchmark's nprobe; 24 sampled queries checked against the oracle."""
+    zp = os.path.join(DATA, "ivf.npz")
+    if not os.path.exists(zp):
+        pytest.skip("data/vmf1m/ivf.npz not built (python -m oracle.build_index vmf1m --what ivf)")
+    z = np.load(zp)
+    np16, np32 = ivf_nprobe()
+    npb, rr = (np16, 40) if mode == "f16" else (np32, 0)
+    v = ann.ann_ivf_create(big["ix"], z["centroids"], z["list_off"], z["list_ids"])
+    try:
+        say("ivf", mode, "nprobe", npb, "all 10,000 queries on the GPU")
+        q = torch.from_numpy(big["Q"]).to("cuda:0")
+        r = ann.ann_ivf_search(v, q, 10, npb, mode=mode, rerank=rr, want_probes=True, want_stats=True)
+        torch.cuda.synchronize()
+        got = {k_: t.cpu().numpy() for k_, t in r.items()}
+    finally:
+        v.close()
+    sample = np.random.default_rng(5).choice(big["Q"].shape[0], 24, replace=False)
+    st = oracle.dense_store(big["X16"], "ip", "f16") if mode == "f16" else oracle.dense_store(big["X"], "ip")
+    ref = oracle.ivf_search(st, z["centroids"], z["list_off"], z["list_ids"], big["Q"][sample], 10, npb,
+                            rerank_f32=big["X"] if rr else None, rerank_depth=rr)
+    assert np.array_equal(got["probes"][sample], ref["probes"])
+    assert np.array_equal(got["stats"][sample], ref["stats"])
+    assert np.array_equal(got["ids"][sample], ref["ids"])
+    assert np.array_equal(got["dists"][sample], ref["keys"])
+    if big["gt"] is not None:
+        rec = oracle.recall_at_k(got["ids"], big["gt"], 10)
+        say(f"ivf {mode} recall@10 {rec:.4f}")
+        assert rec >= 0.95
