@@ -373,8 +373,7 @@ int ann_pq_encode(const float* X, int64_t n, int32_t d, const float* codebook, i
 /*
  * An inverted-file index, the index family the paper names beside graphs
  * (Section 1) and plans to add (Section 5).  The coarse quantizer is a set of
- * nlist FP32 centroids (k-means over whole vectors, e.g. ann_pq_train with
- * m = 1 or the oracle's training); list l holds the rows whose nearest
+ * nlist FP32 centroids (k-means over whole vectors: ann_ivf_train below); list l holds the rows whose nearest
  * centroid is l.  The IVF index searches the rows (or PQ codes) of an
  * existing ann_index, which must outlive it; it adds only the centroids and
  * the lists to device memory.
@@ -423,6 +422,41 @@ typedef struct ann_ivf_batch {
   int32_t* out_probes;
   int32_t* out_stats;
 } ann_ivf_batch;
+
+/*
+ * Construction of the lists on the device (k-means over whole vectors, the
+ * procedure ann_pq_train applies per subspace, with the same arithmetic and
+ * rules: FP64 squared L2 distances in ascending dimension order, first
+ * minimum, FP64 means in ascending sample order rounded once, empty clusters
+ * re-seeded by error).  The results are fixed bit for bit by the inputs.
+ *
+ * ann_ivf_train: Lloyd's iterations on the sample rows; centroid j starts at
+ * sample point init[j].
+ *   X              device f32[n][d]
+ *   sample         device i64[ns], row ids into X (ns >= nlist; checked on
+ *                  the host, which copies them once)
+ *   init           device i64[nlist], positions into sample
+ *   out_centroids  device f32[nlist][d]; 1 <= nlist <= 8192
+ *   out_iters      optional host i32: iterations run (max_iter when the
+ *                  assignment never settled)
+ * Allocates its scratch (12 bytes per sample point) and frees it before
+ * returning; synchronizes `stream`.
+ *
+ * ann_ivf_assign: out_list[r] = the nearest centroid of row r.  X device
+ * f32[n][d], centroids device f32[nlist][d], out_list device i32[n].
+ * Asynchronous on `stream` (NULL: the null stream, blocking).
+ *
+ * ann_ivf_group (host only): the lists of an assignment, ids ascending inside
+ * each list.  list host i32[n] with values in [0, nlist); list_off host
+ * i64[nlist + 1]; list_ids host i32[n].
+ */
+int ann_ivf_train(const float* X, int64_t n, int32_t d, const int64_t* sample, int64_t ns,
+                  const int64_t* init, int32_t nlist, int32_t max_iter, float* out_centroids,
+                  int32_t* out_iters, void* stream);
+int ann_ivf_assign(const float* X, int64_t n, int32_t d, const float* centroids, int32_t nlist,
+                   int32_t* out_list, void* stream);
+int ann_ivf_group(const int32_t* list, int64_t n, int32_t nlist, int64_t* list_off,
+                  int32_t* list_ids);
 
 int ann_ivf_create(ann_index* ix, int32_t nlist, const float* centroids, const int64_t* list_off,
                    const int32_t* list_ids, ann_ivf** out);

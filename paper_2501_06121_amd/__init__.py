@@ -102,6 +102,9 @@ SIGNATURES = {
     "ann_graph_info": ([P, P], C.c_int),
     "ann_graph_export": ([P, P, P, P, P], C.c_int),
     "ann_graph_free": ([P], C.c_int),
+    "ann_ivf_train": ([P, I64, I32, P, I64, P, I32, I32, P, P, P], C.c_int),
+    "ann_ivf_assign": ([P, I64, I32, P, I32, P, P], C.c_int),
+    "ann_ivf_group": ([P, I64, I32, P, P], C.c_int),
     "ann_ivf_create": ([P, I32, P, P, P, P], C.c_int),
     "ann_ivf_free": ([P], C.c_int),
     "ann_ivf_search": ([P, P, P], C.c_int),
@@ -462,6 +465,37 @@ class Ivf:
             self.close()
         except Exception:
             pass
+
+
+def ann_ivf_train(X, sample, init, nlist, max_iter=25, stream=None):
+    """k-means of the coarse quantizer on the device.  X cuda f32 [n, d];
+    sample, init cuda i64.  Returns (centroids cuda f32 [nlist, d], iterations)."""
+    torch = _torch()
+    n, d = X.shape
+    cent = torch.empty((nlist, d), dtype=torch.float32, device=X.device)
+    it = C.c_int32(0)
+    _check(lib().ann_ivf_train(_dptr(X), n, d, _dptr(sample), sample.shape[0], _dptr(init), int(nlist),
+                               int(max_iter), _dptr(cent), C.byref(it), _stream_handle(stream)))
+    return cent, int(it.value)
+
+
+def ann_ivf_assign(X, centroids, stream=None):
+    """Nearest centroid of every row (cuda i32 [n])."""
+    torch = _torch()
+    n, d = X.shape
+    out = torch.empty((n,), dtype=torch.int32, device=X.device)
+    _check(lib().ann_ivf_assign(_dptr(X), n, d, _dptr(centroids), centroids.shape[0], _dptr(out),
+                                _stream_handle(stream)))
+    return out
+
+
+def ann_ivf_group(assign, nlist):
+    """Host lists of an assignment: (list_off i64[nlist+1], list_ids i32[n])."""
+    a = _np(assign, np.int32)
+    off = np.empty(nlist + 1, np.int64)
+    ids = np.empty(a.size, np.int32)
+    _check(lib().ann_ivf_group(_hptr(a), a.size, int(nlist), _hptr(off), _hptr(ids)))
+    return off, ids
 
 
 def ann_ivf_create(index, centroids, list_off, list_ids):

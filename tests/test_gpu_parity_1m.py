@@ -229,3 +229,29 @@ def test_ivf_full_batch_sampled_bitexact(big, mode):
         rec = oracle.recall_at_k(got["ids"], big["gt"], 10)
         say(f"ivf {mode} recall@10 {rec:.4f}")
         assert rec >= 0.95
+
+
+def test_ivf_training_and_assignment_at_full_size(big):
+    """The device trains the 1,024 coarse centroids on the 100,000-row sample and
+    assigns all 1,000,000 rows, equal to the oracle's stored index."""
+    zp = os.path.join(DATA, "ivf.npz")
+    if not os.path.exists(zp):
+        pytest.skip("data/vmf1m/ivf.npz not built (python -m oracle.build_index vmf1m --what ivf)")
+    import time
+    z = np.load(zp)
+    nlist = z["centroids"].shape[0]
+    sample, init = synth.ivf_sample(0, big["X"].shape[0], 100_000, nlist)
+    Xd = torch.from_numpy(big["X"]).to("cuda:0")
+    t = time.perf_counter()
+    cent, iters = ann.ann_ivf_train(Xd, torch.from_numpy(sample).to("cuda:0"),
+                                    torch.from_numpy(init).to("cuda:0"), nlist, max_iter=25)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    asg = ann.ann_ivf_assign(Xd, cent)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    say(f"ivf trained in {t1 - t:.2f} s ({iters} iterations), 1M rows assigned in {t2 - t1:.3f} s")
+    assert iters == int(z["iters"])
+    assert np.array_equal(cent.cpu().numpy(), z["centroids"])
+    off, ids = ann.ann_ivf_group(asg.cpu().numpy(), nlist)
+    assert np.array_equal(off, z["list_off"]) and np.array_equal(ids, z["list_ids"])
