@@ -220,15 +220,16 @@ def ivf_row(ann, torch, ivf, mode, Qd, k, nprobe, rerank, stream, gt, d, nlist, 
             "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": nb}
 
 
-def serve_latency(ann, ix, Q, k, ef, mode, rerank, qps_peak, seconds=3.0, seed=0):
+def serve_latency(ann, ix, Q, k, ef, mode, rerank, qps_peak, seconds=3.0, seed=0, streams=2,
+                  max_batch=2048):
     """Open-loop Poisson arrivals at half the measured peak; p50/p99 ms."""
     import synth
     rate = max(100.0, 0.5 * qps_peak)
     n_req = int(min(Q.shape[0] * 4, max(200, rate * seconds)))
     t_arr, qidx, _, _ = synth.arrivals(seed, n_req, rate, k_choices=(k,), ef_choices=(ef,),
                                        n_pool=Q.shape[0])
-    srv = ann.Server(ix, mode=mode, rerank=rerank, max_inflight=8192, max_batch=2048, streams=2,
-                     k_max=max(k, 10), ef_max=ef)
+    srv = ann.Server(ix, mode=mode, rerank=rerank, max_inflight=8192, max_batch=max_batch,
+                     streams=streams, k_max=max(k, 10), ef_max=ef)
     lat = []
     try:
         t0 = time.perf_counter()
