@@ -7,8 +7,9 @@
 //  * ivf_probe: one wavefront per query scores the query against every FP32
 //    centroid (squared L2 in the fixed FP32 order of a dense FP32 row) and
 //    sorts the (key, list id) pairs in LDS; the first nprobe are the probes;
-//  * ivf_scan: one wavefront per query walks its probed lists 64 rows at a
-//    time, scores them with the search kernel's scoring policy and merges the
+//  * ivf_scan: one wavefront per query walks its probed lists (in ascending
+//    list order, so that the queries in flight share rows in the caches) 64
+//    rows at a time, scores them with the search kernel's scoring policy and merges the
 //    rows that beat the current kk-th best into a sorted list of kk entries
 //    in LDS (kk = max(k, rerank depth)).  The list then takes the optional
 //    FP32 rerank and is written out.
@@ -102,6 +103,7 @@ struct ScanLds {
   uint32_t* ti1;
   float* sk;
   uint32_t* si;
+  uint32_t* pmask;                // probed lists, one bit per list
 };
 
 __device__ ScanLds scan_carve(char* base, const SearchParams& p, const IvfArgs& v) {
@@ -115,6 +117,7 @@ __device__ ScanLds scan_carve(char* base, const SearchParams& p, const IvfArgs& 
   L.s.q = (float*)take(sizeof(float) * p.q_lds_floats);
   L.s.lut = (float*)take(sizeof(float) * (p.mode == MODE_PQ ? p.pq_m * 256 : 0));
   L.s.rk = (float*)take(sizeof(float) * (p.rerank > 0 ? v.kk : 0));
+  L.pmask = (uint32_t*)take(4 * (size_t)((v.nlist + 31) / 32));
   L.tk0 = (float*)take(sizeof(float) * v.kk);
   L.ti0 = (uint32_t*)take(sizeof(uint32_t) * v.kk);
   L.tk1 = (float*)take(sizeof(float) * v.kk);
@@ -128,6 +131,7 @@ size_t scan_lds_bytes(const SearchParams& p, const IvfArgs& v) {
   b += r16(sizeof(float) * p.q_lds_floats);
   b += r16(sizeof(float) * (p.mode == MODE_PQ ? p.pq_m * 256 : 0));
   b += r16(sizeof(float) * (p.rerank > 0 ? v.kk : 0));
+  b += r16(4 * (size_t)((v.nlist + 31) / 32));
   b += 4 * r16(4 * (size_t)v.kk);
   return b;
 }
@@ -159,58 +163,72 @@ __global__ void __launch_bounds__(64) ivf_scan(SearchParams p, IvfArgs v) {
   Policy pol;
   pol.prep(p, s, q);
 
+  // The probed lists are scanned in ascending list order, not in probe
+  // order: the kept entries do not depend on the order (a strict total order
+  // on unique ids), and queries in flight then sweep the rows together, so
+  // that rows one query brings into the caches serve the others.
+  const int words = (v.nlist + 31) / 32;
+  for (int w = lane; w < words; w += 64) L.pmask[w] = 0u;
+  __syncthreads();
+  for (int t = lane; t < v.np; t += 64) {
+    const int l = v.probes[q * v.nprobe + t];
+    if (l >= 0 && l < v.nlist) atomicOr(&L.pmask[l >> 5], 1u << (l & 31));
+  }
+  __syncthreads();
   int cnt = 0, cur = 0, evals = 0;
-  for (int t = 0; t < v.np; ++t) {
-    const int l = uniform_int(v.probes[q * v.nprobe + t]);
-    if (l < 0 || l >= v.nlist) continue;   // unordered (NaN) probe keys can leave a pad entry
-    const int64_t b = v.list_off[l], e = v.list_off[l + 1];
-    for (int64_t base = b; base < e; base += 64) {
-      const int m = (int)min<int64_t>(64, e - base);
-      if (lane < m) s.cid[lane] = v.list_ids[base + lane];
-      __syncthreads();
-      pol.score(p, s, m);
-      __syncthreads();
-      evals += m;
-      const float key = lane < m ? s.ckey[lane] : __builtin_inff();
-      const uint32_t id = lane < m ? (uint32_t)s.cid[lane] : 0xFFFFFFFFu;
-      const float* ck = cur ? L.tk1 : L.tk0;
-      const uint32_t* ci = cur ? L.ti1 : L.ti0;
-      bool pass = lane < m;
-      if (cnt == v.kk) pass = pass && kid_lt(key, id, ck[v.kk - 1], ci[v.kk - 1]);
-      const uint64_t mask = ballot(pass);
-      if (mask == 0) continue;
-      // rank of each new entry among the new entries
-      const int ns = __popcll(mask);
-      int r = 0;
-      for (uint64_t mm = mask; mm; mm &= mm - 1) {
-        const int j = __builtin_ctzll(mm);
-        const float kj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(key), j));
-        const uint32_t ij = (uint32_t)__builtin_amdgcn_readlane((int)id, j);
-        r += kid_lt(kj, ij, key, id) ? 1 : 0;
+  for (int w = 0; w < words; ++w) {
+    uint32_t bits = L.pmask[w];
+    bits = (uint32_t)uniform_int((int)bits);
+    for (; bits; bits &= bits - 1u) {
+      const int l = w * 32 + __builtin_ctz(bits);
+      const int64_t b = v.list_off[l], e = v.list_off[l + 1];
+      for (int64_t base = b; base < e; base += 64) {
+        const int m = (int)min<int64_t>(64, e - base);
+        if (lane < m) s.cid[lane] = v.list_ids[base + lane];
+        __syncthreads();
+        pol.score(p, s, m);
+        __syncthreads();
+        evals += m;
+        const float key = lane < m ? s.ckey[lane] : __builtin_inff();
+        const uint32_t id = lane < m ? (uint32_t)s.cid[lane] : 0xFFFFFFFFu;
+        const float* ck = cur ? L.tk1 : L.tk0;
+        const uint32_t* ci = cur ? L.ti1 : L.ti0;
+        bool pass = lane < m;
+        if (cnt == v.kk) pass = pass && kid_lt(key, id, ck[v.kk - 1], ci[v.kk - 1]);
+        const uint64_t mask = ballot(pass);
+        if (mask == 0) continue;
+        // rank of each new entry among the new entries
+        const int ns = __popcll(mask);
+        int r = 0;
+        for (uint64_t mm = mask; mm; mm &= mm - 1) {
+          const int j = __builtin_ctzll(mm);
+          const float kj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(key), j));
+          const uint32_t ij = (uint32_t)__builtin_amdgcn_readlane((int)id, j);
+          r += kid_lt(kj, ij, key, id) ? 1 : 0;
+        }
+        if (pass) { L.sk[r] = key; L.si[r] = id; }
+        __syncthreads();
+        // merge both sorted runs into the other buffer, keeping the first kk
+        float* nk = cur ? L.tk0 : L.tk1;
+        uint32_t* ni = cur ? L.ti0 : L.ti1;
+        for (int i = lane; i < cnt; i += 64) {
+          const float a = ck[i];
+          const uint32_t ai = ci[i];
+          const int pos = i + count_less(L.sk, L.si, ns, a, ai);
+          if (pos < v.kk) { nk[pos] = a; ni[pos] = ai; }
+        }
+        if (lane < ns) {
+          const float a = L.sk[lane];
+          const uint32_t ai = L.si[lane];
+          const int pos = lane + count_less(ck, ci, cnt, a, ai);
+          if (pos < v.kk) { nk[pos] = a; ni[pos] = ai; }
+        }
+        __syncthreads();
+        cnt = min(v.kk, cnt + ns);
+        cur ^= 1;
       }
-      if (pass) { L.sk[r] = key; L.si[r] = id; }
-      __syncthreads();
-      // merge both sorted runs into the other buffer, keeping the first kk
-      float* nk = cur ? L.tk0 : L.tk1;
-      uint32_t* ni = cur ? L.ti0 : L.ti1;
-      for (int i = lane; i < cnt; i += 64) {
-        const float a = ck[i];
-        const uint32_t ai = ci[i];
-        const int pos = i + count_less(L.sk, L.si, ns, a, ai);
-        if (pos < v.kk) { nk[pos] = a; ni[pos] = ai; }
-      }
-      if (lane < ns) {
-        const float a = L.sk[lane];
-        const uint32_t ai = L.si[lane];
-        const int pos = lane + count_less(ck, ci, cnt, a, ai);
-        if (pos < v.kk) { nk[pos] = a; ni[pos] = ai; }
-      }
-      __syncthreads();
-      cnt = min(v.kk, cnt + ns);
-      cur ^= 1;
     }
   }
-
   const float* fk = cur ? L.tk1 : L.tk0;
   const uint32_t* fi = cur ? L.ti1 : L.ti0;
   const int k = v.k;
