@@ -11,9 +11,10 @@
 //   are free of bank conflicts; the next stage is loaded into registers while
 //   the current one is multiplied.  The block becomes approximate keys (-dot,
 //   or |x|^2 - 2 dot for L2: |q|^2 is the same for every row of a query) in a
-//   tile that reuses the stage buffers, and each query merges the survivors
-//   of its threshold into a sorted top-64 list in LDS.  At the end the lists
-//   go to scratch memory: 64 candidates per (query, range).
+//   tile that reuses the stage buffers, and each query merges the rows that
+//   beat the (k + 17)-th entry of its sorted list (64 entries, in LDS) into
+//   it.  At the end the lists go to scratch memory: 64 candidates per (query,
+//   range), of which the first k + 17 are exact.
 // Stage 2 (bf_finish): one wavefront per query merges the candidate lists of
 //   all ranges into the approximate top-64, re-scores the best k + 16 with the
 //   FP32 rows in the same fixed order as the search kernel, sorts them by
@@ -23,6 +24,8 @@
 //   candidate that was not re-scored.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "ann.h"
 #include "internal.h"
@@ -140,6 +143,7 @@ struct BfParams {
   int64_t nq;
   int64_t rows_per_range;
   int nranges;
+  int admit;             // a row enters a list when it beats the list's admit-th entry
   float* cand_key;       // [nq][nranges][KC]
   int32_t* cand_id;
 };
@@ -261,27 +265,42 @@ __global__ void __launch_bounds__(256) bf_tiles(BfParams p) {
     __syncthreads();
     // the next tile's first stage is in flight while the lists are merged
     if (t0 + BN < r_end) load_stage(p, q0, t0 + BN, r_end, 0, regs);
-    // each wave merges its 32 queries, 64 columns at a time
-    for (int rr = 0; rr < BM / 4; ++rr) {
-      const int row = wave * (BM / 4) + rr;
-      if (q0 + row >= p.nq) break;
-#pragma unroll
-      for (int half = 0; half < BN / 64; ++half) {
-        const int col = half * 64 + lane;
-        const float thr_k = lk[row][KC - 1];
-        const int thr_i = li[row][KC - 1];
-        float k = tile[row * TLD + col];
-        // columns past the range are empty entries (+inf, largest id)
-        int id = (t0 + col < r_end) ? (int)(t0 + col) : 0x7FFFFFFF;
-        const bool keep = kid_less(k, id, thr_k, thr_i);
-        const uint64_t km = __ballot(keep);
-        if (!km) continue;
-        if (__builtin_popcountll(km) > 8) {
-          if (!keep) { k = __builtin_inff(); id = 0x7FFFFFFF; }
-          merge_list(lk[row], li[row], k, id);
-        } else {
-          insert_few(lk[row], li[row], k, id, km);
+    // each wave merges its 32 queries, 64 columns at a time.  First every
+    // lane screens one (query, half tile) against that query's admission
+    // entry; only the flagged pairs take the wave-wide path (a later merge
+    // only lowers the entry, so an unflagged pair stays out)
+    static_assert(BN == 128 && BM / 4 == 32, "one lane per (query, half tile) of the wave");
+    bool hit = false;
+    {
+      const int row = wave * (BM / 4) + (lane >> 1);
+      const int c0 = (lane & 1) * 64;
+      if (q0 + row < p.nq) {
+        const float thr_k = lk[row][p.admit - 1];
+        const int thr_i = li[row][p.admit - 1];
+        for (int c = 0; c < 64; ++c) {
+          const int col = c0 + c;
+          const int id = (t0 + col < r_end) ? (int)(t0 + col) : 0x7FFFFFFF;
+          hit = hit | kid_less(tile[row * TLD + col], id, thr_k, thr_i);
         }
+      }
+    }
+    for (uint64_t todo = __ballot(hit); todo; todo &= todo - 1) {
+      const int j = __builtin_ctzll(todo);
+      const int row = wave * (BM / 4) + (j >> 1);
+      const int col = (j & 1) * 64 + lane;
+      const float thr_k = lk[row][p.admit - 1];
+      const int thr_i = li[row][p.admit - 1];
+      float k = tile[row * TLD + col];
+      // columns past the range are empty entries (+inf, largest id)
+      int id = (t0 + col < r_end) ? (int)(t0 + col) : 0x7FFFFFFF;
+      const bool keep = kid_less(k, id, thr_k, thr_i);
+      const uint64_t km = __ballot(keep);
+      if (!km) continue;
+      if (__builtin_popcountll(km) > 8) {
+        if (!keep) { k = __builtin_inff(); id = 0x7FFFFFFF; }
+        merge_list(lk[row], li[row], k, id);
+      } else {
+        insert_few(lk[row], li[row], k, id, km);
       }
     }
   }
@@ -461,6 +480,11 @@ extern "C" int ann_bruteforce(const ann_index* cix, const float* queries, int64_
   p.X = ix->x_f32; p.x2 = x2; p.n = ix->n; p.d = ix->d; p.metric = ix->metric;
   p.Q = queries; p.nq = nq; p.nranges = nranges;
   p.rows_per_range = (ix->n + nranges - 1) / nranges;
+  // bf_finish re-scores the best k + 16 of the merged lists and certifies
+  // them against the next one, so each range needs its exact best k + 17
+  // only: rows that do not beat the (k + 17)-th entry of their range's list
+  // are not inserted (entries further down may then be stale).
+  p.admit = std::min(KC, k + kRescore + 1);
   p.cand_key = ckey; p.cand_id = cid;
   const dim3 grid((unsigned)((nq + BM - 1) / BM), (unsigned)nranges);
   hipLaunchKernelGGL(bf_tiles, grid, dim3(256), 0, st, p);
