@@ -39,6 +39,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK = 157.3
+FP32_VECTOR_PEAK = 157.3
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -215,9 +216,15 @@ def ivf_row(ann, torch, ivf, mode, Qd, k, nprobe, rerank, stream, gt, d, nlist, 
     rec = recall(tm.out["ids"].cpu().numpy(), gt, k) if gt is not None else None
     nb = ivf_bytes(tm.out["stats"].cpu().numpy(), mode, d, k, rerank, nlist)
     gbs = nb / (ms / 1e3) / 1e9
+    evals = float(tm.out["stats"][:, 0].double().sum().item())
+    tflops = 2.0 * evals * d / (ms / 1e3) / 1e12
+    shared = mode != "pq" and 4 * min(nprobe, nlist) > nlist
     return {"nprobe": nprobe, "qps": round(nq / (ms / 1e3), 1), "recall@10": rec,
-            "ms_per_step": round(ms, 3), "algorithmic_GBps": round(gbs, 1),
-            "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": nb}
+            "ms_per_step": round(ms, 3),
+            "scan": "8 queries per workgroup share LDS tiles" if shared else "one query per workgroup",
+            "algorithmic_GBps": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "bytes_per_launch": nb, "tflops": round(tflops, 2),
+            "frac_of_fp32_vector_peak": round(tflops / FP32_VECTOR_PEAK, 4)}
 
 
 def serve_latency(ann, ix, Q, k, ef, mode, rerank, qps_peak, seconds=3.0, seed=0, streams=2,

@@ -404,6 +404,13 @@ int ann_pq_encode(const float* X, int64_t n, int32_t d, const float* codebook, i
  *                order, -1 beyond nlist
  *   out_stats    optional device i32[nq][2]: distance evaluations (rows
  *                scanned), lists probed
+ *   group        queries per workgroup of the list scan, 0..16.  0: the
+ *                default, 8 in the dense modes when nprobe > nlist / 4, else
+ *                1.  With group > 1 (dense modes only) the workgroup stages
+ *                each list probed by any of its queries in LDS once and every
+ *                query that probes it scores it from there; with 1 each query
+ *                reads its rows from device memory.  The results are the
+ *                same for every group.
  * Asynchronous on `stream` (NULL: the index's stream, and the call waits).
  * Without out_probes the probe lists go to a scratch buffer the IVF object
  * owns (4 bytes per query and probe, grown on demand); batches on different
@@ -421,6 +428,7 @@ typedef struct ann_ivf_batch {
   float* out_dists;
   int32_t* out_probes;
   int32_t* out_stats;
+  int32_t group;
 } ann_ivf_batch;
 
 /*

@@ -82,7 +82,7 @@ class AnnCompletion(C.Structure):
 class AnnIvfBatch(C.Structure):
     _fields_ = [("mode", I32), ("rerank", I32), ("nq", I64), ("queries", P), ("k", I32),
                 ("nprobe", I32), ("out_ids", P), ("out_dists", P), ("out_probes", P),
-                ("out_stats", P)]
+                ("out_stats", P), ("group", I32)]
 
 
 SIGNATURES = {
@@ -514,7 +514,7 @@ def ann_ivf_free(ivf):
 
 
 def ann_ivf_search(ivf, queries, k, nprobe, mode="f32", rerank=0, want_probes=False,
-                   want_stats=False, stream=None, out=None):
+                   want_stats=False, stream=None, out=None, group=0):
     """IVF search of cuda float32 queries [nq, d].  Returns a dict of tensors
     (ids, dists[, probes][, stats]).  Blocking unless a stream is given."""
     torch = _torch()
@@ -535,6 +535,7 @@ def ann_ivf_search(ivf, queries, k, nprobe, mode="f32", rerank=0, want_probes=Fa
     b.out_ids, b.out_dists = _dptr(res["ids"]), _dptr(res["dists"])
     b.out_probes = _dptr(res.get("probes"))
     b.out_stats = _dptr(res.get("stats"))
+    b.group = int(group)
     _check(lib().ann_ivf_search(ivf.handle, C.byref(b), _stream_handle(stream)))
     return res
 

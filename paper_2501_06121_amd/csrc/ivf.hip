@@ -3,7 +3,7 @@
 // (Section 5), searched with the same representations and keys as the HNSW
 // path (FP32 / FP16 / BF16 / FP8 rows, PQ codes, optional FP32 rerank).
 //
-// A batch runs two kernels:
+// A batch runs two kernels (plus, for the dense modes, a choice of scan):
 //  * ivf_probe: one wavefront per query scores the query against every FP32
 //    centroid (squared L2 in the fixed FP32 order of a dense FP32 row) and
 //    sorts the (key, list id) pairs in LDS; the first nprobe are the probes;
@@ -12,7 +12,12 @@
 //    rows at a time, scores them with the search kernel's scoring policy and merges the
 //    rows that beat the current kk-th best into a sorted list of kk entries
 //    in LDS (kk = max(k, rerank depth)).  The list then takes the optional
-//    FP32 rerank and is written out.
+//    FP32 rerank and is written out;
+//  * ivf_scan_shared (dense modes, the default when a query probes more than
+//    a quarter of the lists): up to 16 queries (8 by default) per workgroup
+//    stage each list of the union of their probes in LDS once and each wave
+//    scores the tile for its own query, so that a row is read from device
+//    memory once per workgroup instead of once per query.
 // The rows of a list are read where they are (no per-list copy), so every
 // representation of the index serves the IVF search without extra memory.
 #include <hip/hip_runtime.h>
@@ -32,6 +37,9 @@ namespace ann {
 namespace {
 
 constexpr int kMaxLists = 8192;   // probe sort in LDS: 8 bytes per list
+constexpr int kMaxGroup = 16;     // queries per workgroup of the shared scan (1024 threads)
+constexpr int kAutoGroup = 8;     // the dense modes' default
+constexpr int kCopyBatch = 8;     // 16-byte chunks per thread in flight while staging a tile
 
 struct IvfArgs {
   int nlist, nprobe, np;          // np = min(nprobe, nlist)
@@ -42,6 +50,10 @@ struct IvfArgs {
   const int32_t* list_ids;        // [n]
   int32_t* probes;                // [nq][nprobe]
   int32_t* stats;                 // [nq][2] or NULL
+  int group;                      // queries (wavefronts) per workgroup of the shared scan
+  int wave_lds;                   // LDS bytes of one wave's region (multiple of 16)
+  int tile_rows;                  // rows per LDS tile of the shared scan (<= 64)
+  int tile_bytes;                 // tile_rows * row bytes
 };
 
 // ---------------------------------------------------------------------------
@@ -148,87 +160,57 @@ __device__ __forceinline__ int count_less(const float* ak, const uint32_t* ai, i
   return lo;
 }
 
-template <class Policy>
-__global__ void __launch_bounds__(64) ivf_scan(SearchParams p, IvfArgs v) {
-  extern __shared__ __align__(16) char lds_raw[];
-  const ScanLds L = scan_carve(lds_raw, p, v);
-  const Lds& s = L.s;
-  const int64_t q = blockIdx.x;
+// Merges one batch of scored rows (one per lane; lanes with `pass` enter)
+// into the wave's sorted list of kk entries: the new entries are ranked among
+// themselves with lane reads, then both sorted runs are merged into the other
+// list buffer (merge path), keeping the first kk.  Wave-level ordering only.
+__device__ __forceinline__ void merge_batch(const ScanLds& L, int kk, int& cnt, int& cur, float key,
+                                            uint32_t id, bool pass) {
   const int lane = lane_id();
-  if (p.q_lds_floats > 0) {
-    const float* qrow = p.queries + (size_t)q * p.d;
-    for (int i = lane; i < p.q_lds_floats; i += 64) s.q[i] = (i < p.d) ? qrow[i] : 0.0f;
+  const uint64_t mask = ballot(pass);
+  if (mask == 0) return;
+  const float* ck = cur ? L.tk1 : L.tk0;
+  const uint32_t* ci = cur ? L.ti1 : L.ti0;
+  const int ns = __popcll(mask);
+  int r = 0;
+  for (uint64_t mm = mask; mm; mm &= mm - 1) {
+    const int j = __builtin_ctzll(mm);
+    const float kj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(key), j));
+    const uint32_t ij = (uint32_t)__builtin_amdgcn_readlane((int)id, j);
+    r += kid_lt(kj, ij, key, id) ? 1 : 0;
   }
-  __syncthreads();
-  Policy pol;
-  pol.prep(p, s, q);
+  if (pass) { L.sk[r] = key; L.si[r] = id; }
+  wave_sync();
+  float* nk = cur ? L.tk0 : L.tk1;
+  uint32_t* ni = cur ? L.ti0 : L.ti1;
+  for (int i = lane; i < cnt; i += 64) {
+    const float a = ck[i];
+    const uint32_t ai = ci[i];
+    const int pos = i + count_less(L.sk, L.si, ns, a, ai);
+    if (pos < kk) { nk[pos] = a; ni[pos] = ai; }
+  }
+  if (lane < ns) {
+    const float a = L.sk[lane];
+    const uint32_t ai = L.si[lane];
+    const int pos = lane + count_less(ck, ci, cnt, a, ai);
+    if (pos < kk) { nk[pos] = a; ni[pos] = ai; }
+  }
+  wave_sync();
+  cnt = min(kk, cnt + ns);
+  cur ^= 1;
+}
 
-  // The probed lists are scanned in ascending list order, not in probe
-  // order: the kept entries do not depend on the order (a strict total order
-  // on unique ids), and queries in flight then sweep the rows together, so
-  // that rows one query brings into the caches serve the others.
-  const int words = (v.nlist + 31) / 32;
-  for (int w = lane; w < words; w += 64) L.pmask[w] = 0u;
-  __syncthreads();
-  for (int t = lane; t < v.np; t += 64) {
-    const int l = v.probes[q * v.nprobe + t];
-    if (l >= 0 && l < v.nlist) atomicOr(&L.pmask[l >> 5], 1u << (l & 31));
-  }
-  __syncthreads();
-  int cnt = 0, cur = 0, evals = 0;
-  for (int w = 0; w < words; ++w) {
-    uint32_t bits = L.pmask[w];
-    bits = (uint32_t)uniform_int((int)bits);
-    for (; bits; bits &= bits - 1u) {
-      const int l = w * 32 + __builtin_ctz(bits);
-      const int64_t b = v.list_off[l], e = v.list_off[l + 1];
-      for (int64_t base = b; base < e; base += 64) {
-        const int m = (int)min<int64_t>(64, e - base);
-        if (lane < m) s.cid[lane] = v.list_ids[base + lane];
-        __syncthreads();
-        pol.score(p, s, m);
-        __syncthreads();
-        evals += m;
-        const float key = lane < m ? s.ckey[lane] : __builtin_inff();
-        const uint32_t id = lane < m ? (uint32_t)s.cid[lane] : 0xFFFFFFFFu;
-        const float* ck = cur ? L.tk1 : L.tk0;
-        const uint32_t* ci = cur ? L.ti1 : L.ti0;
-        bool pass = lane < m;
-        if (cnt == v.kk) pass = pass && kid_lt(key, id, ck[v.kk - 1], ci[v.kk - 1]);
-        const uint64_t mask = ballot(pass);
-        if (mask == 0) continue;
-        // rank of each new entry among the new entries
-        const int ns = __popcll(mask);
-        int r = 0;
-        for (uint64_t mm = mask; mm; mm &= mm - 1) {
-          const int j = __builtin_ctzll(mm);
-          const float kj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(key), j));
-          const uint32_t ij = (uint32_t)__builtin_amdgcn_readlane((int)id, j);
-          r += kid_lt(kj, ij, key, id) ? 1 : 0;
-        }
-        if (pass) { L.sk[r] = key; L.si[r] = id; }
-        __syncthreads();
-        // merge both sorted runs into the other buffer, keeping the first kk
-        float* nk = cur ? L.tk0 : L.tk1;
-        uint32_t* ni = cur ? L.ti0 : L.ti1;
-        for (int i = lane; i < cnt; i += 64) {
-          const float a = ck[i];
-          const uint32_t ai = ci[i];
-          const int pos = i + count_less(L.sk, L.si, ns, a, ai);
-          if (pos < v.kk) { nk[pos] = a; ni[pos] = ai; }
-        }
-        if (lane < ns) {
-          const float a = L.sk[lane];
-          const uint32_t ai = L.si[lane];
-          const int pos = lane + count_less(ck, ci, cnt, a, ai);
-          if (pos < v.kk) { nk[pos] = a; ni[pos] = ai; }
-        }
-        __syncthreads();
-        cnt = min(v.kk, cnt + ns);
-        cur ^= 1;
-      }
-    }
-  }
+// The end of a query, by its wave: the optional FP32 rerank of the first
+// min(max(R, k), cnt) kept entries (4 rows at a time, 64 lanes per row in the
+// fixed FP32 order), the ranking by (key, id), the k results with padding, and
+// the statistics.
+__device__ __forceinline__ void finish_query(const SearchParams& p, const IvfArgs& v,
+                                             const ScanLds& L, int64_t q, int cnt, int cur,
+                                             int evals) {
+  const Lds& s = L.s;
+  // the FP32 query: its LDS copy, or (shared scan) device memory
+  const float* qv = p.q_lds_floats > 0 ? s.q : p.queries + (size_t)q * p.d;
+  const int lane = lane_id();
   const float* fk = cur ? L.tk1 : L.tk0;
   const uint32_t* fi = cur ? L.ti1 : L.ti0;
   const int k = v.k;
@@ -257,7 +239,7 @@ __global__ void __launch_bounds__(64) ivf_scan(SearchParams p, IvfArgs v) {
         for (int t = 0; t < 4; ++t) {
           const int g = lane + 64 * t;
           if (g < nch) {
-            const float* qc = s.q + g * 4;
+            const float* qc = qv + g * 4;
             if (p.metric == METRIC_IP) {
               acc = __builtin_fmaf(qc[0], __uint_as_float(raw[u][t].x), acc);
               acc = __builtin_fmaf(qc[1], __uint_as_float(raw[u][t].y), acc);
@@ -279,7 +261,7 @@ __global__ void __launch_bounds__(64) ivf_scan(SearchParams p, IvfArgs v) {
         if (lane == 0 && i0 + u < R) s.rk[i0 + u] = (p.metric == METRIC_IP) ? -acc : acc;
       }
     }
-    __syncthreads();
+    wave_sync();
     for (int i = lane; i < R; i += 64) {
       const float ki = s.rk[i];
       const uint32_t ii = fi[i];
@@ -308,44 +290,209 @@ __global__ void __launch_bounds__(64) ivf_scan(SearchParams p, IvfArgs v) {
   }
 }
 
+// The probed lists of query q as a bit mask in the wave's LDS region.
+__device__ __forceinline__ void probe_mask(const IvfArgs& v, const ScanLds& L, int64_t q) {
+  const int lane = lane_id();
+  const int words = (v.nlist + 31) / 32;
+  for (int w = lane; w < words; w += 64) L.pmask[w] = 0u;
+  wave_sync();
+  for (int t = lane; t < v.np; t += 64) {
+    const int l = v.probes[q * v.nprobe + t];
+    if (l >= 0 && l < v.nlist) atomicOr(&L.pmask[l >> 5], 1u << (l & 31));
+  }
+  wave_sync();
+}
+
+// One query per workgroup (one wavefront): the rows are read from device
+// memory where they are.  The probed lists are scanned in ascending list
+// order, not in probe order: the kept entries do not depend on the order (a
+// strict total order on unique ids), and the queries in flight then sweep
+// the rows together, so that rows one query brings into the caches serve the
+// others.
+template <class Policy>
+__global__ void __launch_bounds__(64) ivf_scan(SearchParams p, IvfArgs v) {
+  extern __shared__ __align__(16) char lds_raw[];
+  const ScanLds L = scan_carve(lds_raw, p, v);
+  const Lds& s = L.s;
+  const int64_t q = blockIdx.x;
+  const int lane = lane_id();
+  if (p.q_lds_floats > 0) {
+    const float* qrow = p.queries + (size_t)q * p.d;
+    for (int i = lane; i < p.q_lds_floats; i += 64) s.q[i] = (i < p.d) ? qrow[i] : 0.0f;
+  }
+  __syncthreads();
+  Policy pol;
+  pol.prep(p, s, q);
+  probe_mask(v, L, q);
+  const int words = (v.nlist + 31) / 32;
+  int cnt = 0, cur = 0, evals = 0;
+  for (int w = 0; w < words; ++w) {
+    for (uint32_t bits = (uint32_t)uniform_int((int)L.pmask[w]); bits; bits &= bits - 1u) {
+      const int l = w * 32 + __builtin_ctz(bits);
+      const int64_t b = v.list_off[l], e = v.list_off[l + 1];
+      for (int64_t base = b; base < e; base += 64) {
+        const int m = (int)min<int64_t>(64, e - base);
+        if (lane < m) s.cid[lane] = v.list_ids[base + lane];
+        __syncthreads();
+        pol.score(p, s, m);
+        __syncthreads();
+        evals += m;
+        const float key = lane < m ? s.ckey[lane] : __builtin_inff();
+        const uint32_t id = lane < m ? (uint32_t)s.cid[lane] : 0xFFFFFFFFu;
+        const float* ck = cur ? L.tk1 : L.tk0;
+        const uint32_t* ci = cur ? L.ti1 : L.ti0;
+        bool pass = lane < m;
+        if (cnt == v.kk) pass = pass && kid_lt(key, id, ck[v.kk - 1], ci[v.kk - 1]);
+        merge_batch(L, v.kk, cnt, cur, key, id, pass);
+      }
+    }
+  }
+  finish_query(p, v, L, q, cnt, cur, evals);
+}
+
+// v.group queries per workgroup (one wavefront each), dense modes.  The
+// workgroup walks the union of its queries' probed lists in ascending order
+// and stages each list, v.tile_rows rows at a time, in LDS once; every wave
+// whose query probes that list then scores the tile from LDS with the same
+// scoring policy (same keys as from device memory) and merges it into its own
+// list.  A row is read from device memory once per workgroup instead of once
+// per query.
+template <class Policy>
+__global__ void __launch_bounds__(1024) ivf_scan_shared(SearchParams p, IvfArgs v) {
+  extern __shared__ __align__(16) char lds_raw[];
+  const size_t row_bytes = (size_t)p.nchunks * 16;
+  const int words = (v.nlist + 31) / 32;
+  char* tile = lds_raw;                                              // [tile_rows][row_bytes]
+  uint32_t* tile_ids = (uint32_t*)(lds_raw + v.tile_bytes);          // [64]
+  float* tile_scale = (float*)(lds_raw + v.tile_bytes + 256);        // [64] (FP8)
+  uint32_t* umask = (uint32_t*)(lds_raw + v.tile_bytes + 512);       // [words]
+  char* regions = lds_raw + v.tile_bytes + 512 + ((4 * (size_t)words + 15) & ~size_t(15));
+  const int wave = wave_id();
+  const int lane = lane_id();
+  const ScanLds L = scan_carve(regions + (size_t)wave * v.wave_lds, p, v);
+  const Lds& s = L.s;
+  const int64_t q = (int64_t)blockIdx.x * v.group + wave;
+  const bool active = q < p.nq;
+  Policy pol;
+  if (active) {
+    if (p.q_lds_floats > 0) {
+      const float* qrow = p.queries + (size_t)q * p.d;
+      for (int i = lane; i < p.q_lds_floats; i += 64) s.q[i] = (i < p.d) ? qrow[i] : 0.0f;
+    }
+    pol.prep(p, s, q);
+    probe_mask(v, L, q);
+  } else {
+    for (int w = lane; w < words; w += 64) L.pmask[w] = 0u;
+  }
+  __syncthreads();
+  for (int w = threadIdx.x; w < words; w += blockDim.x) {
+    uint32_t u = 0u;
+    for (int g = 0; g < num_waves(); ++g) u |= scan_carve(regions + (size_t)g * v.wave_lds, p, v).pmask[w];
+    umask[w] = u;
+  }
+  __syncthreads();
+  const int nch = p.nchunks;
+  const char* rows = (const char*)p.rows;
+  int cnt = 0, cur = 0, evals = 0;
+  for (int w = 0; w < words; ++w) {
+    for (uint32_t bits = (uint32_t)uniform_int((int)umask[w]); bits; bits &= bits - 1u) {
+      const int bit = __builtin_ctz(bits);
+      const int l = w * 32 + bit;
+      const bool mine = active && ((L.pmask[w] >> bit) & 1u);
+      const int64_t b = v.list_off[l], e = v.list_off[l + 1];
+      for (int64_t base = b; base < e; base += v.tile_rows) {
+        const int m = (int)min<int64_t>(v.tile_rows, e - base);
+        __syncthreads();                  // every wave is done with the previous tile
+        for (int r = threadIdx.x; r < m; r += blockDim.x) {
+          const int32_t id = v.list_ids[base + r];
+          tile_ids[r] = (uint32_t)id;
+          if (p.mode == MODE_FP8) tile_scale[r] = p.fp8_scale[id];
+        }
+        __syncthreads();
+        // the rows, kCopyBatch 16-byte chunks per thread in flight at once
+        const int total = m * nch;
+        for (int c0 = threadIdx.x; c0 < total; c0 += kCopyBatch * blockDim.x) {
+          uint4 x[kCopyBatch];
+#pragma unroll
+          for (int u = 0; u < kCopyBatch; ++u) {
+            const int c = c0 + u * (int)blockDim.x;
+            x[u] = make_uint4(0u, 0u, 0u, 0u);
+            if (c < total) {
+              const int r = c / nch, g = c - r * nch;
+              x[u] = *(const uint4*)(rows + (size_t)tile_ids[r] * row_bytes + (size_t)g * 16);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < kCopyBatch; ++u) {
+            const int c = c0 + u * (int)blockDim.x;
+            if (c < total) {
+              const int r = c / nch, g = c - r * nch;
+              *(uint4*)(tile + (size_t)r * row_bytes + (size_t)g * 16) = x[u];
+            }
+          }
+        }
+        __syncthreads();
+        if (!mine) continue;
+        if (lane < m) s.cid[lane] = lane;
+        wave_sync();
+        pol.score_rows(p, s, 0, m, tile, tile_scale);
+        wave_sync();
+        evals += m;
+        const float key = lane < m ? s.ckey[lane] : __builtin_inff();
+        const uint32_t id = lane < m ? tile_ids[lane] : 0xFFFFFFFFu;
+        const float* ck = cur ? L.tk1 : L.tk0;
+        const uint32_t* ci = cur ? L.ti1 : L.ti0;
+        bool pass = lane < m;
+        if (cnt == v.kk) pass = pass && kid_lt(key, id, ck[v.kk - 1], ci[v.kk - 1]);
+        merge_batch(L, v.kk, cnt, cur, key, id, pass);
+      }
+    }
+  }
+  if (active) finish_query(p, v, L, q, cnt, cur, evals);
+}
+
 // ---------------------------------------------------------------------------
 // kernel selection
 // ---------------------------------------------------------------------------
 
-template <class Policy>
-const void* scan_sym() { return (const void*)ivf_scan<Policy>; }
+template <class Policy, bool SHARED>
+const void* scan_sym() {
+  if constexpr (SHARED) return (const void*)ivf_scan_shared<Policy>;
+  else return (const void*)ivf_scan<Policy>;
+}
 
-template <int MODE>
+template <int MODE, bool SH>
 const void* scan_dense(int L, int cpl) {
   if (L == 64) {
-    if (cpl <= 1) return scan_sym<Dense<MODE, 64, 1>>();
-    if (cpl <= 2) return scan_sym<Dense<MODE, 64, 2>>();
-    if (cpl <= 3) return scan_sym<Dense<MODE, 64, 3>>();
-    if (cpl <= 4) return scan_sym<Dense<MODE, 64, 4>>();
+    if (cpl <= 1) return scan_sym<Dense<MODE, 64, 1>, SH>();
+    if (cpl <= 2) return scan_sym<Dense<MODE, 64, 2>, SH>();
+    if (cpl <= 3) return scan_sym<Dense<MODE, 64, 3>, SH>();
+    if (cpl <= 4) return scan_sym<Dense<MODE, 64, 4>, SH>();
   } else if (L == 32) {
-    if (cpl <= 1) return scan_sym<Dense<MODE, 32, 1>>();
-    if (cpl <= 2) return scan_sym<Dense<MODE, 32, 2>>();
+    if (cpl <= 1) return scan_sym<Dense<MODE, 32, 1>, SH>();
+    if (cpl <= 2) return scan_sym<Dense<MODE, 32, 2>, SH>();
     if constexpr (MODE != MODE_FP8)
-      if (cpl <= 3) return scan_sym<Dense<MODE, 32, 3>>();
+      if (cpl <= 3) return scan_sym<Dense<MODE, 32, 3>, SH>();
     if constexpr (MODE == MODE_F32)
-      if (cpl <= 4) return scan_sym<Dense<MODE, 32, 4>>();
+      if (cpl <= 4) return scan_sym<Dense<MODE, 32, 4>, SH>();
   } else if (L == 16) {
-    if (cpl <= 1) return scan_sym<Dense<MODE, 16, 1>>();
-    if (cpl <= 2) return scan_sym<Dense<MODE, 16, 2>>();
+    if (cpl <= 1) return scan_sym<Dense<MODE, 16, 1>, SH>();
+    if (cpl <= 2) return scan_sym<Dense<MODE, 16, 2>, SH>();
     if constexpr (MODE == MODE_F32)
-      if (cpl <= 4) return scan_sym<Dense<MODE, 16, 4>>();
+      if (cpl <= 4) return scan_sym<Dense<MODE, 16, 4>, SH>();
   }
   return nullptr;
 }
 
+template <bool SH>
 const void* scan_symbol(const SearchParams& p) {
   const int L = p.lanes_per_row, cpl = (p.nchunks + L - 1) / L;
   switch (p.mode) {
-    case MODE_F32: return scan_dense<MODE_F32>(L, cpl);
-    case MODE_F16: return scan_dense<MODE_F16>(L, cpl);
-    case MODE_BF16: return scan_dense<MODE_BF16>(L, cpl);
-    case MODE_FP8: return scan_dense<MODE_FP8>(L, cpl);
-    case MODE_PQ: return scan_sym<PQ>();
+    case MODE_F32: return scan_dense<MODE_F32, SH>(L, cpl);
+    case MODE_F16: return scan_dense<MODE_F16, SH>(L, cpl);
+    case MODE_BF16: return scan_dense<MODE_BF16, SH>(L, cpl);
+    case MODE_FP8: return scan_dense<MODE_FP8, SH>(L, cpl);
+    case MODE_PQ: return SH ? nullptr : scan_sym<PQ, false>();
   }
   return nullptr;
 }
@@ -360,11 +507,11 @@ const void* probe_symbol(int cpl) {
   return nullptr;
 }
 
-hipError_t launch(const void* fn, int64_t blocks, size_t lds, hipStream_t st, SearchParams& p,
-                  IvfArgs& v) {
+hipError_t launch(const void* fn, int64_t blocks, int threads, size_t lds, hipStream_t st,
+                  SearchParams& p, IvfArgs& v) {
   void* args[] = {&p, &v};
   if (lds > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  return hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(64), args, lds, st);
+  return hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(threads), args, lds, st);
 }
 
 }  // namespace
@@ -474,9 +621,39 @@ extern "C" int ann_ivf_search(ann_ivf* v, const ann_ivf_batch* b, void* stream) 
   A.list_off = v->list_off;
   A.list_ids = v->list_ids;
   A.stats = b->out_stats;
-  const void* scan = scan_symbol(P);
+  if (b->group < 0 || b->group > kMaxGroup)
+    return fail(ANN_EINVAL, "group %d outside [0, %d]", b->group, kMaxGroup);
+  if (P.mode == MODE_PQ && b->group > 1)
+    return fail(ANN_EINVAL, "the PQ scan takes one query per workgroup (group 0 or 1)");
+  // default: share the tiles when a query probes more than a quarter of the
+  // lists (8 such queries overlap enough to pay for the shared staging;
+  // measured on 1M x 768 with 1,024 lists: equal at nprobe 256, 2.6x faster
+  // at nprobe 896, 2x slower at nprobe 64)
+  A.group = b->group ? b->group : (P.mode != MODE_PQ && 4 * A.np > A.nlist ? kAutoGroup : 1);
+  if (b->nq < A.group) A.group = (int)b->nq;
+  auto r16 = [](size_t x) { return (x + 15) & ~size_t(15); };
+  if (A.group > 1) P.q_lds_floats = 0;   // the shared scan reranks from the query in device memory
+  A.wave_lds = (int)r16(scan_lds_bytes(P, A));
+  size_t scan_lds = A.wave_lds;
+  if (A.group > 1) {
+    // the tile takes what the waves leave of half the LDS (two workgroups per
+    // compute unit), at most 64 rows; with less room, the whole LDS
+    const size_t row_bytes = (size_t)P.nchunks * 16;
+    const size_t fixed = 512 + r16(4 * (size_t)((A.nlist + 31) / 32)) + (size_t)A.group * A.wave_lds;
+    auto fit = [&](size_t budget) {
+      const size_t r = budget > fixed ? std::min<size_t>(64, (budget - fixed) / row_bytes) : 0;
+      return (int)(r >= 8 ? r & ~size_t(7) : r);
+    };
+    A.tile_rows = fit(ix->lds_limit / 2);
+    if (A.tile_rows < 8) A.tile_rows = std::max(A.tile_rows, fit(ix->lds_limit));
+    if (A.tile_rows < 1)
+      return fail(ANN_EBUDGET, "on-chip memory of the shared IVF scan: %d queries of %d bytes and rows of %zu bytes",
+                  A.group, A.wave_lds, row_bytes);
+    A.tile_bytes = (int)(A.tile_rows * row_bytes);
+    scan_lds = A.tile_bytes + fixed;
+  }
+  const void* scan = A.group > 1 ? scan_symbol<true>(P) : scan_symbol<false>(P);
   if (!scan) return fail(ANN_EBUDGET, "no IVF scan kernel for mode %d with %d lanes per row", P.mode, P.lanes_per_row);
-  const size_t scan_lds = scan_lds_bytes(P, A);
   if (scan_lds > ix->lds_limit)
     return fail(ANN_EBUDGET, "on-chip memory of the IVF scan: %zu bytes > %zu", scan_lds, ix->lds_limit);
   // the probe kernel scores FP32 centroids with L2 keys, 64 lanes per centroid
@@ -511,8 +688,9 @@ extern "C" int ann_ivf_search(ann_ivf* v, const ann_ivf_batch* b, void* stream) 
     HIP_OR_RETURN(hipStreamWaitEvent(st, v->done, 0), "hipStreamWaitEvent");
     A.probes = v->probes;
   }
-  HIP_OR_RETURN(launch(probe, b->nq, probe_lds, st, C, A), "ivf_probe launch");
-  HIP_OR_RETURN(launch(scan, b->nq, scan_lds, st, P, A), "ivf_scan launch");
+  HIP_OR_RETURN(launch(probe, b->nq, 64, probe_lds, st, C, A), "ivf_probe launch");
+  HIP_OR_RETURN(launch(scan, (b->nq + A.group - 1) / A.group, 64 * A.group, scan_lds, st, P, A),
+                "ivf_scan launch");
   if (!b->out_probes) HIP_OR_RETURN(hipEventRecord(v->done, st), "hipEventRecord");
   if (!stream) HIP_OR_RETURN(hipStreamSynchronize(st), "IVF search");
   return ANN_OK;

@@ -234,18 +234,17 @@ struct Dense {
     return true;
   }
 
-  // keys of the m candidate ids in s.cid[] into s.ckey[]
+  // keys of the candidate rows s.cid[lo..hi) into s.ckey[lo..hi), by the
+  // calling wave; row r is read at rows + r * 16 * nchunks (its FP8 scale at
+  // scale[r])
   template <bool IP>
-  __device__ __forceinline__ void score_impl(const SearchParams& p, const Lds& s, int m) {
+  __device__ __forceinline__ void score_impl(const SearchParams& p, const Lds& s, int lo, int hi,
+                                             const void* rows_base, const float* scale_base) {
     const int lane = lane_id();
     const int j = lane & (L - 1);
     const int grp = lane / L;
     const size_t row_bytes = (size_t)p.nchunks * 16;
-    const char* rows = (const char*)p.rows;
-    // the waves of the workgroup take contiguous shares of the rows
-    const int per = (m + num_waves() - 1) / num_waves();
-    const int lo = wave_id() * per;
-    const int hi = lo + per < m ? lo + per : m;
+    const char* rows = (const char*)rows_base;
     for (int base = lo; base < hi; base += G * U) {
       uint4 raw[U][CPL];
       int rid[U];
@@ -266,7 +265,7 @@ struct Dense {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (base + u * G >= hi) break;
-        const float scale = (MODE == MODE_FP8 && rid[u] >= 0) ? p.fp8_scale[rid[u]] : 1.0f;
+        const float scale = (MODE == MODE_FP8 && rid[u] >= 0) ? scale_base[rid[u]] : 1.0f;
         float acc[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) acc[v] = 0.0f;
@@ -297,9 +296,20 @@ struct Dense {
     }
   }
 
+  // keys of the m candidate ids in s.cid[] into s.ckey[]; the waves of the
+  // workgroup take contiguous shares of the rows
   __device__ __forceinline__ void score(const SearchParams& p, const Lds& s, int m) {
-    if (p.metric == METRIC_IP) score_impl<true>(p, s, m);
-    else score_impl<false>(p, s, m);
+    const int per = (m + num_waves() - 1) / num_waves();
+    const int lo = wave_id() * per;
+    const int hi = lo + per < m ? lo + per : m;
+    score_rows(p, s, lo, hi, p.rows, p.fp8_scale);
+  }
+
+  // the same for rows s.cid[lo..hi) of another row array, by the calling wave
+  __device__ __forceinline__ void score_rows(const SearchParams& p, const Lds& s, int lo, int hi,
+                                             const void* rows, const float* scale) {
+    if (p.metric == METRIC_IP) score_impl<true>(p, s, lo, hi, rows, scale);
+    else score_impl<false>(p, s, lo, hi, rows, scale);
   }
 };
 

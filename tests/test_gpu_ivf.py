@@ -78,19 +78,19 @@ def store_for(s, mode):
     return oracle.pq_store(s["cb"], s["codes"], metric)
 
 
-def run(s, mode, Q, k, nprobe, rerank=0, ivf=None):
+def run(s, mode, Q, k, nprobe, rerank=0, ivf=None, group=0):
     q = torch.from_numpy(np.ascontiguousarray(Q)).to(DEV)
     r = ann.ann_ivf_search(ivf or s["ivf"], q, k, nprobe, mode=mode, rerank=rerank,
-                           want_probes=True, want_stats=True)
+                           want_probes=True, want_stats=True, group=group)
     torch.cuda.synchronize()
     return {k_: t.cpu().numpy() for k_, t in r.items()}
 
 
-def check(s, mode, k, nprobe, rerank=0, Q=None):
+def check(s, mode, k, nprobe, rerank=0, Q=None, group=0):
     Q = s["Q"] if Q is None else Q
     ref = oracle.ivf_search(store_for(s, mode), s["cent"], s["off"], s["ids"], Q, k, nprobe,
                             rerank_f32=s["X"] if rerank else None, rerank_depth=rerank)
-    got = run(s, mode, Q, k, nprobe, rerank)
+    got = run(s, mode, Q, k, nprobe, rerank, group=group)
     assert np.array_equal(got["probes"], ref["probes"]), np.argwhere(got["probes"] != ref["probes"])[:5]
     assert np.array_equal(got["stats"], ref["stats"])
     assert np.array_equal(got["ids"], ref["ids"]), np.argwhere(got["ids"] != ref["ids"])[:5]
@@ -100,15 +100,26 @@ def check(s, mode, k, nprobe, rerank=0, Q=None):
 
 @pytest.mark.parametrize("mode", ["f32", "f16", "bf16", "fp8", "pq"])
 @pytest.mark.parametrize("nprobe", [1, 6, 64])
-def test_l2_modes_bitexact(l2set, mode, nprobe):
-    say("ivf l2 gmm10k", mode, "nprobe", nprobe)
-    check(l2set, mode, 10, nprobe)
+@pytest.mark.parametrize("group", [0, 1])
+def test_l2_modes_bitexact(l2set, mode, nprobe, group):
+    # group 0: the default (the shared scan for the dense modes); 1: one query per workgroup
+    say("ivf l2 gmm10k", mode, "nprobe", nprobe, "group", group)
+    check(l2set, mode, 10, nprobe, group=group)
 
 
 @pytest.mark.parametrize("mode", ["f32", "f16", "bf16", "fp8"])
-def test_ip_768_modes_bitexact(ipset, mode):
-    say("ivf ip 4096 x 768", mode)
-    check(ipset, mode, 10, 5)
+@pytest.mark.parametrize("group", [1, 3, 8, 16])
+def test_ip_768_modes_bitexact(ipset, mode, group):
+    # 64 queries: groups of 3 leave a ragged last workgroup
+    say("ivf ip 4096 x 768", mode, "group", group)
+    check(ipset, mode, 10, 5, group=group)
+
+
+@pytest.mark.parametrize("group", [2, 5, 8, 13])
+def test_shared_scan_with_rerank_and_large_k(ipset, group):
+    say("ivf shared scan, rerank 40 and k 300, group", group)
+    check(ipset, "f16", 10, 9, rerank=40, group=group)
+    check(ipset, "bf16", 300, 3, group=group)
 
 
 @pytest.mark.parametrize("mode,rerank", [("f16", 40), ("bf16", 40), ("pq", 100), ("fp8", 100)])
@@ -175,12 +186,14 @@ def test_bad_arguments(l2set):
     q = torch.from_numpy(l2set["Q"]).to(DEV)
     for kw, code in ((dict(k=0), ann.ANN_EINVAL), (dict(k=ann.ANN_K_MAX + 1), ann.ANN_EINVAL),
                      (dict(nprobe=0), ann.ANN_EINVAL), (dict(mode="sparse"), ann.ANN_EUNSUP),
-                     (dict(rerank=ann.ANN_K_MAX + 1), ann.ANN_EINVAL)):
+                     (dict(rerank=ann.ANN_K_MAX + 1), ann.ANN_EINVAL),
+                     (dict(group=17), ann.ANN_EINVAL), (dict(group=-1), ann.ANN_EINVAL),
+                     (dict(mode="pq", group=2), ann.ANN_EINVAL)):
         args = dict(k=10, nprobe=4, mode="f16")
         args.update(kw)
         with pytest.raises(ann.AnnError) as e:
             ann.ann_ivf_search(l2set["ivf"], q, args["k"], args["nprobe"], mode=args["mode"],
-                               rerank=args.get("rerank", 0))
+                               rerank=args.get("rerank", 0), group=args.get("group", 0))
         assert e.value.code == code, kw
     cent, off, ids = l2set["cent"], l2set["off"], l2set["ids"]
     bad = ids.copy()
