@@ -259,6 +259,86 @@ def serve_latency(ann, ix, Q, k, ef, mode, rerank, qps_peak, seconds=3.0, seed=0
     return float(np.percentile(lat, 50)), float(np.percentile(lat, 99)), rate
 
 
+def serve_mix(ann, torch, n=None, seconds=3.0, rates=(5000, 10000, 20000, 35000, 50000),
+              rerank=40):
+    """The serving mix: dense vectors of 96 dimensions from a 4,096-centre
+    Gaussian mixture (10,000,000 by default), HNSW M = 32, efC = 200 built on
+    the device, FP16 rows + FP32 rerank; open-loop Poisson arrivals at each
+    rate, every request with k in {10, 100} and ef in {64, 128, 256, 512}
+    drawn uniformly.  Reports p50/p99 latency and the completion rate per
+    offered rate, and checks that served results equal a direct batch search
+    of the same requests."""
+    import synth
+    spec = synth.WORKLOADS["gmm10m"]
+    n = n or spec["n"]
+    t = time.perf_counter()
+    X = synth.dense_base(spec, n=n)
+    Q = synth.dense_queries(spec)
+    log(f"serving mix: regenerated {X.shape} + {Q.shape} in {time.perf_counter() - t:.1f}s")
+    Xd = torch.from_numpy(X).to("cuda:0")
+    u = synth.level_uniforms(0, n)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    g = ann.ann_hnsw_build(Xd, spec["metric"], spec["M"], spec["efc"], u, seq_prefix=2000,
+                           batch_frac=0.02, batch_cap=2048)
+    build_s = time.perf_counter() - t
+    del Xd
+    torch.cuda.empty_cache()
+    log(f"serving mix: graph built on the device in {build_s:.1f}s (max level {g.max_level})")
+    ix = ann.ann_index_create(g, spec["metric"], X.shape[1], x_f32=X,
+                              x_f16=X.astype(np.float16).view(np.uint16))
+    out = {"n": int(n), "d": int(X.shape[1]), "M": spec["M"], "efc": spec["efc"],
+           "build_seconds": round(build_s, 2), "rerank": rerank, "rates": []}
+    for i_rate, rate in enumerate(rates):
+        n_req = int(rate * seconds)
+        t_arr, qidx, ks, efs = synth.arrivals(i_rate, n_req, rate, k_choices=(10, 100),
+                                              ef_choices=(64, 128, 256, 512), n_pool=Q.shape[0])
+        srv = ann.Server(ix, mode="f16", rerank=rerank, max_inflight=16384, max_batch=2048,
+                         streams=2, k_max=100, ef_max=512)
+        lat = np.zeros(n_req)
+        got = {}
+        try:
+            t0 = time.perf_counter()
+            i = done = 0
+            while done < n_req:
+                now = time.perf_counter() - t0
+                while i < n_req and t_arr[i] <= now:
+                    if not srv.submit(i, Q[qidx[i]], int(ks[i]), int(efs[i])):
+                        break
+                    i += 1
+                for c in srv.poll():
+                    lat[c["tag"]] = (c["t_done"] - c["t_submit"]) * 1e3
+                    if c["tag"] < 512:
+                        got[c["tag"]] = c["ids"]
+                    done += 1
+                if i < n_req and t_arr[i] > now:
+                    time.sleep(min(2e-4, t_arr[i] - now))
+            wall = time.perf_counter() - t0
+        finally:
+            srv.close()
+        # the first 512 requests again, as one direct batch with per-query k and ef
+        m = min(512, n_req)
+        r = ann.ann_search_ex(ix, "f16", queries=torch.from_numpy(Q[qidx[:m]]).to("cuda:0"),
+                              k=torch.from_numpy(ks[:m]).to("cuda:0"),
+                              ef=torch.from_numpy(efs[:m]).to("cuda:0"), rerank=rerank,
+                              k_max=100, ef_max=512)
+        direct = r["ids"].cpu().numpy()
+        same = sum(bool(np.array_equal(got[j], direct[j, :ks[j]])) for j in range(m))
+        # recall@10 of those requests against the exact scan on matrix cores
+        gt, _, _ = ann.ann_bruteforce(ix, torch.from_numpy(Q[qidx[:m]]).to("cuda:0"), 10)
+        rec = recall(direct[:, :10], gt.cpu().numpy(), 10)
+        row = {"offered_qps": rate, "requests": n_req, "completed_qps": round(n_req / wall, 1),
+               "p50_ms": round(float(np.percentile(lat, 50)), 3),
+               "p99_ms": round(float(np.percentile(lat, 99)), 3),
+               "served_equal_direct": f"{same}/{m}", "recall@10_first_512": round(rec, 4)}
+        out["rates"].append(row)
+        log(f"serving mix at {rate} QPS offered: {row['completed_qps']:.0f} QPS completed, "
+            f"p50 {row['p50_ms']:.2f} ms, p99 {row['p99_ms']:.2f} ms, same as direct {same}/{m}, "
+            f"recall@10 {rec:.4f}")
+    ix.close()
+    return out
+
+
 def host_threads():
     """Threads the host gives this process (OMP_NUM_THREADS when set, else the CPUs it may use)."""
     env = os.environ.get("OMP_NUM_THREADS")
@@ -333,6 +413,10 @@ def main():
     ap.add_argument("--ivf-only", action="store_true",
                     help="time only the IVF search at its chosen nprobe (for profiling)")
     ap.add_argument("--no-ivf", action="store_true")
+    ap.add_argument("--serve-mix", action="store_true",
+                    help="only the serving mix: 10M x 96 graph built on the device, Poisson "
+                    "arrivals at 5k-50k QPS with mixed k and ef; prints one JSON line")
+    ap.add_argument("--serve-mix-n", type=int, default=None)
     ap.add_argument("--sweep", default=None, help="comma-separated ef values: write the sweep file")
     ap.add_argument("--sweep-out", default=None, help="where the sweep JSON goes "
                     "(default profiles/<workload>_ef_sweep.json)")
@@ -352,6 +436,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": a.copy_calibration, "copies": 3}), flush=True)
+        return
+    if a.serve_mix:
+        print(json.dumps({"serve_mix": serve_mix(ann, torch, n=a.serve_mix_n)}), flush=True)
         return
     spec, g, X, Q, gt = load_workload(a.workload, a.nq)
     if a.build:
