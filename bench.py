@@ -339,6 +339,62 @@ def serve_mix(ann, torch, n=None, seconds=3.0, rates=(5000, 10000, 20000, 35000,
     return out
 
 
+def sparse_sweep(ann, torch, efs=(100, 200, 300, 400, 500), nq=10000):
+    """The sparse workload: 200,000 documents of the 1M-document SPLADE-shaped
+    set (30,522 terms, ~120 nonzeros per document, ~40 per query, Zipf(1.1)
+    term ids, log-normal weights), inner product, the oracle-built graph
+    (M = 32, efC = 200); all queries in one persistent launch per ef."""
+    import synth
+    spec = synth.WORKLOADS["splade1m"]
+    ddir = os.path.join(ROOT, "data", "splade1m_n200000")
+    g = read_graph(os.path.join(ddir, "graph.npz"))
+    n = g.n
+    ip, ids, vals = synth.sparse_zipf(0, n, spec["nnz_doc"], vocab=spec["vocab"])
+    qp, qi, qv = synth.sparse_zipf(0, nq, spec["nnz_query"], vocab=spec["vocab"], which="queries")
+    # the ground truth file holds the exact top-100 of the 1,000-query draw
+    # (the generator draws whole arrays, so it is not a prefix of this draw)
+    gt = np.load(os.path.join(ddir, "gt.npz"))["ids"]
+    rp, ri, rv = synth.sparse_zipf(0, gt.shape[0], spec["nnz_query"], vocab=spec["vocab"], which="queries")
+    rq = (torch.from_numpy(rp).to("cuda:0"), torch.from_numpy(ri.view(np.int16)).to("cuda:0"),
+          torch.from_numpy(rv).to("cuda:0"))
+    ix = ann.ann_index_create(g, "ip", spec["vocab"], sp_indptr=ip, sp_ids=ids, sp_vals=vals)
+    sq = (torch.from_numpy(qp).to("cuda:0"), torch.from_numpy(qi.view(np.int16)).to("cuda:0"),
+          torch.from_numpy(qv).to("cuda:0"))
+    nnz = np.diff(ip)
+    stream = torch.cuda.Stream()
+    out = {"docs": int(n), "queries": int(nq), "mean_nnz_doc": round(float(nnz.mean()), 1),
+           "mean_nnz_query": round(float(np.diff(qp).mean()), 1), "rows": []}
+    for ef in efs:
+        r = ann.ann_search_ex(ix, "sparse", sparse=sq, k=10, ef=ef, want_stats=True)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(3):
+            ann.ann_search_ex(ix, "sparse", sparse=sq, k=10, ef=ef, stream=stream, out=r)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 3
+        st = r["stats"].cpu().numpy()
+        rr = ann.ann_search_ex(ix, "sparse", sparse=rq, k=10, ef=ef)
+        rec = recall(rr["ids"].cpu().numpy(), gt, 10)
+        # bytes a search must read: per evaluated document its indptr pair and
+        # its nonzeros (u16 id + f32 weight), per expansion a neighbour list
+        evals = st[:, 0].astype(np.int64).sum()
+        exps = st[:, 1].astype(np.int64).sum()
+        doc_bytes = 16 + 6 * float(nnz.mean())
+        nb = evals * doc_bytes + exps * g.M0 * 4 + nq * (6 * float(np.diff(qp).mean()) + 8 + 120)
+        gbs = nb / (ms / 1e3) / 1e9
+        row = {"ef": ef, "qps": round(nq / (ms / 1e3), 1),
+               f"recall@10_{gt.shape[0]}_queries": round(rec, 4),
+               "ms_per_step": round(ms, 3), "algorithmic_GBps": round(gbs, 1),
+               "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+        out["rows"].append(row)
+        log(f"sparse ef={ef}: {row['qps']:.0f} QPS, recall@10 {rec:.4f}, {gbs:.0f} GB/s algorithmic")
+    ix.close()
+    return out
+
+
 def host_threads():
     """Threads the host gives this process (OMP_NUM_THREADS when set, else the CPUs it may use)."""
     env = os.environ.get("OMP_NUM_THREADS")
@@ -417,6 +473,8 @@ def main():
                     help="only the serving mix: 10M x 96 graph built on the device, Poisson "
                     "arrivals at 5k-50k QPS with mixed k and ef; prints one JSON line")
     ap.add_argument("--serve-mix-n", type=int, default=None)
+    ap.add_argument("--sparse", action="store_true",
+                    help="only the sparse workload (200k SPLADE-shaped documents), ef 100-500")
     ap.add_argument("--sweep", default=None, help="comma-separated ef values: write the sweep file")
     ap.add_argument("--sweep-out", default=None, help="where the sweep JSON goes "
                     "(default profiles/<workload>_ef_sweep.json)")
@@ -439,6 +497,9 @@ def main():
         return
     if a.serve_mix:
         print(json.dumps({"serve_mix": serve_mix(ann, torch, n=a.serve_mix_n)}), flush=True)
+        return
+    if a.sparse:
+        print(json.dumps({"sparse": sparse_sweep(ann, torch)}), flush=True)
         return
     spec, g, X, Q, gt = load_workload(a.workload, a.nq)
     if a.build:
