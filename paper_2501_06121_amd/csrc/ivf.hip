@@ -40,6 +40,11 @@ constexpr int kMaxLists = 8192;   // probe sort in LDS: 8 bytes per list
 constexpr int kMaxGroup = 16;     // queries per workgroup of the shared scan (1024 threads)
 constexpr int kAutoGroup = 8;     // the dense modes' default
 constexpr int kCopyBatch = 8;     // 16-byte chunks per thread in flight while staging a tile
+// Workgroups of the shared scan one compute unit should hold (the LDS share
+// the tile is sized for).
+#ifndef ANN_IVF_SHARED_WG_PER_CU
+#define ANN_IVF_SHARED_WG_PER_CU 2
+#endif
 
 struct IvfArgs {
   int nlist, nprobe, np;          // np = min(nprobe, nlist)
@@ -632,10 +637,11 @@ extern "C" int ann_ivf_search(ann_ivf* v, const ann_ivf_batch* b, void* stream) 
   A.group = b->group ? b->group : (P.mode != MODE_PQ && 4 * A.np > A.nlist ? kAutoGroup : 1);
   if (b->nq < A.group) A.group = (int)b->nq;
   auto r16 = [](size_t x) { return (x + 15) & ~size_t(15); };
-  if (A.group > 1) P.q_lds_floats = 0;   // the shared scan reranks from the query in device memory
-  A.wave_lds = (int)r16(scan_lds_bytes(P, A));
-  size_t scan_lds = A.wave_lds;
+  const int q_lds = P.q_lds_floats;
+  size_t scan_lds = 0;
   if (A.group > 1) {
+    P.q_lds_floats = 0;   // the shared scan reranks from the query in device memory
+    A.wave_lds = (int)r16(scan_lds_bytes(P, A));
     // the tile takes what the waves leave of half the LDS (two workgroups per
     // compute unit), at most 64 rows; with less room, the whole LDS
     const size_t row_bytes = (size_t)P.nchunks * 16;
@@ -644,13 +650,22 @@ extern "C" int ann_ivf_search(ann_ivf* v, const ann_ivf_batch* b, void* stream) 
       const size_t r = budget > fixed ? std::min<size_t>(64, (budget - fixed) / row_bytes) : 0;
       return (int)(r >= 8 ? r & ~size_t(7) : r);
     };
-    A.tile_rows = fit(ix->lds_limit / 2);
+    A.tile_rows = fit(ix->lds_limit / ANN_IVF_SHARED_WG_PER_CU);
     if (A.tile_rows < 8) A.tile_rows = std::max(A.tile_rows, fit(ix->lds_limit));
-    if (A.tile_rows < 1)
+    if (A.tile_rows >= 1) {
+      A.tile_bytes = (int)(A.tile_rows * row_bytes);
+      scan_lds = A.tile_bytes + fixed;
+    } else if (b->group) {
       return fail(ANN_EBUDGET, "on-chip memory of the shared IVF scan: %d queries of %d bytes and rows of %zu bytes",
                   A.group, A.wave_lds, row_bytes);
-    A.tile_bytes = (int)(A.tile_rows * row_bytes);
-    scan_lds = A.tile_bytes + fixed;
+    } else {
+      A.group = 1;                       // the default falls back to one query per workgroup
+      P.q_lds_floats = q_lds;
+    }
+  }
+  if (A.group == 1) {
+    A.wave_lds = (int)r16(scan_lds_bytes(P, A));
+    scan_lds = A.wave_lds;
   }
   const void* scan = A.group > 1 ? scan_symbol<true>(P) : scan_symbol<false>(P);
   if (!scan) return fail(ANN_EBUDGET, "no IVF scan kernel for mode %d with %d lanes per row", P.mode, P.lanes_per_row);

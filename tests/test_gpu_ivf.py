@@ -206,3 +206,15 @@ def test_bad_arguments(l2set):
     with pytest.raises(ann.AnnError) as e:
         ann.ann_ivf_create(l2set["ix"], cent, bad_off, ids)
     assert e.value.code == ann.ANN_EFORMAT
+
+
+def test_default_group_falls_back_when_the_shared_layout_does_not_fit(l2set):
+    # k = rerank = 1024 with every list probed: eight 1024-entry lists per
+    # workgroup do not fit beside a tile, so the default takes one query per
+    # workgroup, and an explicit group of 8 is refused
+    say("ivf k 1024 rerank 1024 nprobe 64 (default group)")
+    check(l2set, "f16", 1024, 64, rerank=1024, Q=l2set["Q"][:20])
+    q = torch.from_numpy(l2set["Q"][:20]).to(DEV)
+    with pytest.raises(ann.AnnError) as e:
+        ann.ann_ivf_search(l2set["ivf"], q, 1024, 64, mode="f16", rerank=1024, group=8)
+    assert e.value.code == ann.ANN_EBUDGET
