@@ -373,10 +373,10 @@ int ann_pq_encode(const float* X, int64_t n, int32_t d, const float* codebook, i
 /*
  * An inverted-file index, the index family the paper names beside graphs
  * (Section 1) and plans to add (Section 5).  The coarse quantizer is a set of
- * nlist FP32 centroids (k-means over whole vectors: ann_ivf_train below); list l holds the rows whose nearest
- * centroid is l.  The IVF index searches the rows (or PQ codes) of an
- * existing ann_index, which must outlive it; it adds only the centroids and
- * the lists to device memory.
+ * nlist FP32 centroids (k-means over whole vectors: ann_ivf_train below);
+ * list l holds the rows whose nearest centroid is l.  The IVF index searches
+ * the rows (or PQ codes) of an existing ann_index, which must outlive it; it
+ * adds only the centroids and the lists to device memory.
  *
  * ann_ivf_create (host arrays, copied; the caller may free them afterwards):
  *   centroids  f32[nlist][d], finite; 1 <= nlist <= 8192, d a multiple of 4
@@ -414,7 +414,13 @@ int ann_pq_encode(const float* X, int64_t n, int32_t d, const float* codebook, i
  * Asynchronous on `stream` (NULL: the index's stream, and the call waits).
  * Without out_probes the probe lists go to a scratch buffer the IVF object
  * owns (4 bytes per query and probe, grown on demand); batches on different
- * streams are ordered on it by an event.
+ * streams are ordered on it by an event, and calls on one IVF object are
+ * serialized by the library.  Errors: ANN_EINVAL (arguments, group > 1 in PQ
+ * mode), ANN_EUNSUP (sparse mode, missing arrays), ANN_EBUDGET (an explicit
+ * group whose tiles and lists do not fit the LDS), ANN_ENOMEM, ANN_EHIP.
+ *
+ * ann_ivf_free waits for the device and frees the IVF object's memory (not
+ * the index's).
  */
 typedef struct ann_ivf ann_ivf;
 typedef struct ann_ivf_batch {

@@ -131,3 +131,18 @@ def test_server_rejects_bad_arguments_on_the_host():
     assert L.ann_server_submit(None, None) == ann.ANN_EINVAL
     assert L.ann_server_poll(None, None, 0) == -ann.ANN_EINVAL
     assert L.ann_server_destroy(None) == ann.ANN_OK
+
+
+def test_ivf_group_matches_the_oracle_grouping():
+    """ann_ivf_group is host code: the lists of an assignment, ids ascending."""
+    import numpy as np
+    import oracle
+    rng = np.random.default_rng(9)
+    for n, nlist in ((0, 3), (1, 1), (1000, 7), (5000, 300)):
+        a = rng.integers(0, nlist, n).astype(np.int32)
+        off, ids = ann.ann_ivf_group(a, nlist)
+        roff, rids = oracle.ivf_lists(a, nlist)
+        assert np.array_equal(off, roff) and np.array_equal(ids, rids)
+    with pytest.raises(ann.AnnError) as e:
+        ann.ann_ivf_group(np.array([0, 2], np.int32), 2)
+    assert e.value.code == ann.ANN_EINVAL
