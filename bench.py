@@ -395,18 +395,37 @@ def sparse_sweep(ann, torch, efs=(100, 200, 300, 400, 500), nq=10000):
     return out
 
 
-def pq_sweep(ann, torch, spec, g, X, Q, gt, efs=(100, 200, 400, 1024, 4096), rerank=100):
-    """PQ-compressed HNSW on the 1M x 768 set: 64 subspaces x 256 centroids
-    (the stored codebook and codes), ADC traversal with per-query tables in
-    LDS, FP32 rerank of the first 100; all queries in one launch per ef."""
+def quant_sweep(ann, torch, spec, g, X, Q, gt, efs=(100, 200, 400, 1024, 4096), rerank=100):
+    """The quantized representations on the 1M x 768 set, FP32 rerank of the
+    first 100, all queries in one launch per ef: PQ with 64 subspaces x 256
+    centroids (the stored codebook and codes; ADC with per-query tables in
+    LDS), and FP8-E4M3 rows with per-row scales (encoded on the device)."""
     z = np.load(os.path.join(ROOT, "data", "vmf1m", "pq.npz"))
     cb, codes = z["codebook"], z["codes"]
     ix = ann.ann_index_create(g, spec["metric"], X.shape[1], x_f32=X, pq_codebook=cb, pq_codes=codes)
     Qd = torch.from_numpy(Q).to("cuda:0")
     stream = torch.cuda.Stream()
-    out = {"pq_m": int(cb.shape[0]), "ksub": int(cb.shape[1]), "rerank": rerank, "rows": []}
+    out = {"pq": {"pq_m": int(cb.shape[0]), "ksub": int(cb.shape[1]), "rerank": rerank, "rows": []},
+           "fp8": {"rerank": rerank, "rows": []}}
+    Xd = torch.from_numpy(X).to("cuda:0")
+    f8, s8 = ann.ann_encode_fp8(Xd)
+    torch.cuda.synchronize()
+    del Xd
+    ix8 = ann.ann_index_create(g, spec["metric"], X.shape[1], x_f32=X, x_fp8=f8.cpu().numpy(),
+                               fp8_scale=s8.cpu().numpy())
+    del f8, s8
+    for mode, index in (("pq", ix), ("fp8", ix8)):
+        out[mode]["rows"] = quant_rows(ann, torch, index, mode, Qd, gt, g, X, efs, rerank, stream,
+                                       cb.shape[0])
+    ix.close()
+    ix8.close()
+    return out
+
+
+def quant_rows(ann, torch, ix, mode, Qd, gt, g, X, efs, rerank, stream, pq_m):
+    rows = []
     for ef in efs:
-        tm = Timed(ann, torch, ix, "pq", Qd, 10, ef, rerank, stream)
+        tm = Timed(ann, torch, ix, mode, Qd, 10, ef, rerank, stream)
         ms, _ = tm.run(2, 1)
         rec = recall(tm.out["ids"].cpu().numpy(), gt, 10) if gt is not None else None
         st = tm.step(stats=True)
@@ -416,14 +435,14 @@ def pq_sweep(ann, torch, spec, g, X, Q, gt, efs=(100, 200, 400, 1024, 4096), rer
         exps = stats[:, 1].astype(np.int64)
         w = stats[:, 3].astype(np.int64)
         rr = np.minimum(max(rerank, 10), w)
-        nb = int((evals * cb.shape[0] + exps * g.M0 * 4 + rr * X.shape[1] * 4 + X.shape[1] * 4 + 120).sum())
+        per_eval = pq_m if mode == "pq" else row_bytes("fp8", X.shape[1])
+        nb = int((evals * per_eval + exps * g.M0 * 4 + rr * X.shape[1] * 4 + X.shape[1] * 4 + 120).sum())
         gbs = nb / (ms / 1e3) / 1e9
-        row = {"ef": ef, "qps": round(Q.shape[0] / (ms / 1e3), 1), "recall@10": rec,
+        row = {"ef": ef, "qps": round(Qd.shape[0] / (ms / 1e3), 1), "recall@10": rec,
                "ms_per_step": round(ms, 3), "algorithmic_GBps": round(gbs, 1)}
-        out["rows"].append(row)
-        log(f"pq+rerank{rerank} ef={ef}: {row['qps']:.0f} QPS, recall@10 {rec}, {gbs:.0f} GB/s algorithmic")
-    ix.close()
-    return out
+        rows.append(row)
+        log(f"{mode}+rerank{rerank} ef={ef}: {row['qps']:.0f} QPS, recall@10 {rec}, {gbs:.0f} GB/s algorithmic")
+    return rows
 
 
 def host_threads():
@@ -504,8 +523,8 @@ def main():
                     help="only the serving mix: 10M x 96 graph built on the device, Poisson "
                     "arrivals at 5k-50k QPS with mixed k and ef; prints one JSON line")
     ap.add_argument("--serve-mix-n", type=int, default=None)
-    ap.add_argument("--pq", action="store_true",
-                    help="only PQ-ADC + FP32 rerank of 100 on the 1M x 768 set (stored codebook)")
+    ap.add_argument("--quant", action="store_true",
+                    help="only PQ-ADC and FP8 rows + FP32 rerank of 100 on the 1M x 768 set")
     ap.add_argument("--sparse", action="store_true",
                     help="only the sparse workload (200k SPLADE-shaped documents), ef 100-500")
     ap.add_argument("--sweep", default=None, help="comma-separated ef values: write the sweep file")
@@ -535,8 +554,8 @@ def main():
         print(json.dumps({"sparse": sparse_sweep(ann, torch)}), flush=True)
         return
     spec, g, X, Q, gt = load_workload(a.workload, a.nq)
-    if a.pq:
-        print(json.dumps({"pq": pq_sweep(ann, torch, spec, g, X, Q, gt)}), flush=True)
+    if a.quant:
+        print(json.dumps(quant_sweep(ann, torch, spec, g, X, Q, gt)), flush=True)
         return
     if a.build:
         build_bench(ann, torch, spec, g, X)

@@ -368,6 +368,22 @@ int ann_pq_train(const float* X, int64_t n, int32_t d, const int64_t* sample, in
 int ann_pq_encode(const float* X, int64_t n, int32_t d, const float* codebook, int32_t m,
                   int32_t ksub, uint8_t* out_codes, void* stream);
 
+/* ---- FP8 storage copy on the device -------------------------------------- */
+
+/*
+ * The FP8-E4M3 copy of dense rows that ANN_MODE_FP8 searches: row r gets the
+ * scale s_r = max_i |x_ri| / 448 (1 for an all-zero row) and the codes
+ * E4M3(x_ri / s_r), both quotients in FP32; OCP E4M3 (bias 7, 3 mantissa
+ * bits, no infinities, largest finite 448), rounded to nearest even,
+ * saturating at +-448, NaN to 0x7F with its sign.
+ *   X          device f32[n][d]
+ *   out_codes  device u8[n][d]
+ *   out_scale  device f32[n]
+ * Asynchronous on `stream` (NULL: the null stream, blocking).
+ */
+int ann_encode_fp8(const float* X, int64_t n, int32_t d, uint8_t* out_codes, float* out_scale,
+                   void* stream);
+
 /* ---- IVF index (inverted lists over a coarse quantizer) ------------------ */
 
 /*

@@ -102,6 +102,7 @@ SIGNATURES = {
     "ann_graph_info": ([P, P], C.c_int),
     "ann_graph_export": ([P, P, P, P, P], C.c_int),
     "ann_graph_free": ([P], C.c_int),
+    "ann_encode_fp8": ([P, I64, I32, P, P, P], C.c_int),
     "ann_ivf_train": ([P, I64, I32, P, I64, P, I32, I32, P, P, P], C.c_int),
     "ann_ivf_assign": ([P, I64, I32, P, I32, P, P], C.c_int),
     "ann_ivf_group": ([P, I64, I32, P, P], C.c_int),
@@ -465,6 +466,16 @@ class Ivf:
             self.close()
         except Exception:
             pass
+
+
+def ann_encode_fp8(X, stream=None):
+    """FP8-E4M3 rows with per-row scales of cuda f32 [n, d]: (codes u8 [n, d], scale f32 [n])."""
+    torch = _torch()
+    n, d = X.shape
+    codes = torch.empty((n, d), dtype=torch.uint8, device=X.device)
+    scale = torch.empty((n,), dtype=torch.float32, device=X.device)
+    _check(lib().ann_encode_fp8(_dptr(X), n, d, _dptr(codes), _dptr(scale), _stream_handle(stream)))
+    return codes, scale
 
 
 def ann_ivf_train(X, sample, init, nlist, max_iter=25, stream=None):
