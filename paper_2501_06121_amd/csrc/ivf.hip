@@ -40,6 +40,7 @@ constexpr int kMaxLists = 8192;   // probe sort in LDS: 8 bytes per list
 constexpr int kMaxGroup = 16;     // queries per workgroup of the shared scan (1024 threads)
 constexpr int kAutoGroup = 8;     // the dense modes' default
 constexpr int kCopyBatch = 8;     // 16-byte chunks per thread in flight while staging a tile
+constexpr int kIdChunk = 1024;    // list ids (and FP8 scales) staged in LDS at once
 // Workgroups of the shared scan one compute unit should hold (the LDS share
 // the tile is sized for).
 #ifndef ANN_IVF_SHARED_WG_PER_CU
@@ -356,8 +357,9 @@ __global__ void __launch_bounds__(64) ivf_scan(SearchParams p, IvfArgs v) {
 }
 
 // v.group queries per workgroup (one wavefront each), dense modes.  The
-// workgroup walks the union of its queries' probed lists in ascending order
-// and stages each list, v.tile_rows rows at a time, in LDS once; every wave
+// workgroup walks the union of its queries' probed lists in ascending order,
+// stages the list's ids (up to kIdChunk at a time) and then its rows,
+// v.tile_rows at a time, in LDS once; every wave
 // whose query probes that list then scores the tile from LDS with the same
 // scoring policy (same keys as from device memory) and merges it into its own
 // list.  A row is read from device memory once per workgroup instead of once
@@ -368,10 +370,10 @@ __global__ void __launch_bounds__(1024) ivf_scan_shared(SearchParams p, IvfArgs 
   const size_t row_bytes = (size_t)p.nchunks * 16;
   const int words = (v.nlist + 31) / 32;
   char* tile = lds_raw;                                              // [tile_rows][row_bytes]
-  uint32_t* tile_ids = (uint32_t*)(lds_raw + v.tile_bytes);          // [64]
-  float* tile_scale = (float*)(lds_raw + v.tile_bytes + 256);        // [64] (FP8)
-  uint32_t* umask = (uint32_t*)(lds_raw + v.tile_bytes + 512);       // [words]
-  char* regions = lds_raw + v.tile_bytes + 512 + ((4 * (size_t)words + 15) & ~size_t(15));
+  uint32_t* list_ids = (uint32_t*)(lds_raw + v.tile_bytes);          // [kIdChunk] of the list
+  float* list_scale = (float*)(lds_raw + v.tile_bytes + 4 * kIdChunk);   // [kIdChunk] (FP8)
+  uint32_t* umask = (uint32_t*)(lds_raw + v.tile_bytes + 8 * kIdChunk);  // [words]
+  char* regions = lds_raw + v.tile_bytes + 8 * kIdChunk + ((4 * (size_t)words + 15) & ~size_t(15));
   const int wave = wave_id();
   const int lane = lane_id();
   const ScanLds L = scan_carve(regions + (size_t)wave * v.wave_lds, p, v);
@@ -405,51 +407,55 @@ __global__ void __launch_bounds__(1024) ivf_scan_shared(SearchParams p, IvfArgs 
       const int l = w * 32 + bit;
       const bool mine = active && ((L.pmask[w] >> bit) & 1u);
       const int64_t b = v.list_off[l], e = v.list_off[l + 1];
-      for (int64_t base = b; base < e; base += v.tile_rows) {
-        const int m = (int)min<int64_t>(v.tile_rows, e - base);
+      for (int64_t c0 = b; c0 < e; c0 += kIdChunk) {
+        // the ids (and FP8 scales) of up to kIdChunk rows of the list, once
+        const int nc = (int)min<int64_t>(kIdChunk, e - c0);
         __syncthreads();                  // every wave is done with the previous tile
-        for (int r = threadIdx.x; r < m; r += blockDim.x) {
-          const int32_t id = v.list_ids[base + r];
-          tile_ids[r] = (uint32_t)id;
-          if (p.mode == MODE_FP8) tile_scale[r] = p.fp8_scale[id];
+        for (int r = threadIdx.x; r < nc; r += blockDim.x) {
+          const int32_t id = v.list_ids[c0 + r];
+          list_ids[r] = (uint32_t)id;
+          if (p.mode == MODE_FP8) list_scale[r] = p.fp8_scale[id];
         }
-        __syncthreads();
-        // the rows, kCopyBatch 16-byte chunks per thread in flight at once
-        const int total = m * nch;
-        for (int c0 = threadIdx.x; c0 < total; c0 += kCopyBatch * blockDim.x) {
-          uint4 x[kCopyBatch];
+        for (int t0 = 0; t0 < nc; t0 += v.tile_rows) {
+          const int m = min(v.tile_rows, nc - t0);
+          __syncthreads();                // ids staged / the previous tile scored
+          // the rows, kCopyBatch 16-byte chunks per thread in flight at once
+          const int total = m * nch;
+          for (int cb = threadIdx.x; cb < total; cb += kCopyBatch * blockDim.x) {
+            uint4 x[kCopyBatch];
 #pragma unroll
-          for (int u = 0; u < kCopyBatch; ++u) {
-            const int c = c0 + u * (int)blockDim.x;
-            x[u] = make_uint4(0u, 0u, 0u, 0u);
-            if (c < total) {
-              const int r = c / nch, g = c - r * nch;
-              x[u] = *(const uint4*)(rows + (size_t)tile_ids[r] * row_bytes + (size_t)g * 16);
+            for (int u = 0; u < kCopyBatch; ++u) {
+              const int c = cb + u * (int)blockDim.x;
+              x[u] = make_uint4(0u, 0u, 0u, 0u);
+              if (c < total) {
+                const int r = c / nch, g = c - r * nch;
+                x[u] = *(const uint4*)(rows + (size_t)list_ids[t0 + r] * row_bytes + (size_t)g * 16);
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < kCopyBatch; ++u) {
+              const int c = cb + u * (int)blockDim.x;
+              if (c < total) {
+                const int r = c / nch, g = c - r * nch;
+                *(uint4*)(tile + (size_t)r * row_bytes + (size_t)g * 16) = x[u];
+              }
             }
           }
-#pragma unroll
-          for (int u = 0; u < kCopyBatch; ++u) {
-            const int c = c0 + u * (int)blockDim.x;
-            if (c < total) {
-              const int r = c / nch, g = c - r * nch;
-              *(uint4*)(tile + (size_t)r * row_bytes + (size_t)g * 16) = x[u];
-            }
-          }
+          __syncthreads();
+          if (!mine) continue;
+          if (lane < m) s.cid[lane] = lane;
+          wave_sync();
+          pol.score_rows(p, s, 0, m, tile, list_scale + t0);
+          wave_sync();
+          evals += m;
+          const float key = lane < m ? s.ckey[lane] : __builtin_inff();
+          const uint32_t id = lane < m ? list_ids[t0 + lane] : 0xFFFFFFFFu;
+          const float* ck = cur ? L.tk1 : L.tk0;
+          const uint32_t* ci = cur ? L.ti1 : L.ti0;
+          bool pass = lane < m;
+          if (cnt == v.kk) pass = pass && kid_lt(key, id, ck[v.kk - 1], ci[v.kk - 1]);
+          merge_batch(L, v.kk, cnt, cur, key, id, pass);
         }
-        __syncthreads();
-        if (!mine) continue;
-        if (lane < m) s.cid[lane] = lane;
-        wave_sync();
-        pol.score_rows(p, s, 0, m, tile, tile_scale);
-        wave_sync();
-        evals += m;
-        const float key = lane < m ? s.ckey[lane] : __builtin_inff();
-        const uint32_t id = lane < m ? tile_ids[lane] : 0xFFFFFFFFu;
-        const float* ck = cur ? L.tk1 : L.tk0;
-        const uint32_t* ci = cur ? L.ti1 : L.ti0;
-        bool pass = lane < m;
-        if (cnt == v.kk) pass = pass && kid_lt(key, id, ck[v.kk - 1], ci[v.kk - 1]);
-        merge_batch(L, v.kk, cnt, cur, key, id, pass);
       }
     }
   }
@@ -645,7 +651,7 @@ extern "C" int ann_ivf_search(ann_ivf* v, const ann_ivf_batch* b, void* stream) 
     // the tile takes what the waves leave of half the LDS (two workgroups per
     // compute unit), at most 64 rows; with less room, the whole LDS
     const size_t row_bytes = (size_t)P.nchunks * 16;
-    const size_t fixed = 512 + r16(4 * (size_t)((A.nlist + 31) / 32)) + (size_t)A.group * A.wave_lds;
+    const size_t fixed = 8 * (size_t)kIdChunk + r16(4 * (size_t)((A.nlist + 31) / 32)) + (size_t)A.group * A.wave_lds;
     auto fit = [&](size_t budget) {
       const size_t r = budget > fixed ? std::min<size_t>(64, (budget - fixed) / row_bytes) : 0;
       return (int)(r >= 8 ? r & ~size_t(7) : r);
