@@ -228,9 +228,13 @@ def ivf_row(ann, torch, ivf, mode, Qd, k, nprobe, rerank, stream, gt, d, nlist, 
 
 
 def serve_latency(ann, ix, Q, k, ef, mode, rerank, qps_peak, seconds=3.0, seed=0, streams=2,
-                  max_batch=2048):
-    """Open-loop Poisson arrivals at half the measured peak; p50/p99 ms."""
+                  max_batch=2048, waves=4):
+    """Open-loop Poisson arrivals at half the measured peak; p50/p99 ms.  At half
+    load fewer queries are in flight, so the server gives each query `waves`
+    wavefronts (4: lower latency than the throughput-optimal 2 at this load,
+    measured; 8 no longer keeps up)."""
     import synth
+    ann.ann_set_launch(ix, mode, waves_per_query=waves)
     rate = max(100.0, 0.5 * qps_peak)
     n_req = int(min(Q.shape[0] * 4, max(200, rate * seconds)))
     t_arr, qidx, _, _ = synth.arrivals(seed, n_req, rate, k_choices=(k,), ef_choices=(ef,),
@@ -255,6 +259,7 @@ def serve_latency(ann, ix, Q, k, ef, mode, rerank, qps_peak, seconds=3.0, seed=0
                 time.sleep(min(2e-4, t_arr[i] - now))
     finally:
         srv.close()
+        ann.ann_set_launch(ix, mode)
     lat = np.array(lat)
     return float(np.percentile(lat, 50)), float(np.percentile(lat, 99)), rate
 
