@@ -182,8 +182,10 @@ int ann_search(const ann_index* ix, const float* queries, int64_t nq, int32_t k,
  *                  (key, id) and the first k returned.  Needs x_f32.
  *   queries        device f32[nq][d] (dense and PQ modes)
  *   q_indptr, q_ids, q_vals   device CSR of the sparse queries (sparse mode):
- *                  i64[nq + 1], u16, f32; ids strictly increasing per query,
- *                  at most 256 nonzeros per query
+ *                  i64[nq + 1], u16, f32; ids strictly increasing per query.
+ *                  The device keeps at most 256 nonzeros of a query (in an
+ *                  LDS hash table); a longer query is cut to its first 256
+ *                  and flagged in out_status (bit 1)
  *   k, ef          device i32[nq] per-query values, or NULL to use k_all /
  *                  ef_all for every query
  *   k_max, ef_max  host-side upper bounds of the per-query values (they size
@@ -191,7 +193,10 @@ int ann_search(const ann_index* ix, const float* queries, int64_t nq, int32_t k,
  *                  exceeds them is clamped and flagged in out_status
  *   out_ids        device i64[nq][k_max]; columns >= k of a row are -1
  *   out_dists      device f32[nq][k_max]; +inf where the id is -1
- *   out_status     optional device i32[nq]: 0 = ok, 1 = k or ef clamped
+ *   out_status     optional device i32[nq], bit flags (0 = ok): bit 0 (1) =
+ *                  k or ef clamped to k_max / ef_max; bit 1 (2) = a sparse
+ *                  query with more than 256 nonzeros was searched with its
+ *                  first 256 (by position) only
  *   out_stats      optional device i32[nq][4]: distance evaluations (all
  *                  layers), layer-0 expansions, layer-0 visited count, |W|
  *   out_visited    optional device i32[nq][visited_cap]: the layer-0 visited
@@ -235,7 +240,8 @@ int ann_search_sparse(const ann_index* ix, const int64_t* q_indptr, const uint16
  * beam together, so a large beam (whose LDS limits the queries per compute
  * unit) still keeps many rows in flight.
  * lanes_per_row (16, 32 or 64) is how many lanes evaluate one dense row
- * together.  beam_buffer is the capacity of the sorted insert buffer that a
+ * together, or, in PQ mode, one candidate of a short run (each lane looks
+ * up 64 / lanes_per_row of its table entries; default 16).  beam_buffer is the capacity of the sorted insert buffer that a
  * large beam uses in front of its sorted list (new entries are merged into
  * the buffer, the buffer into the list only when it fills): 0 lets the
  * library decide (queries with ef above 1024 use one sized from ef and the
@@ -266,12 +272,50 @@ int ann_set_launch(ann_index* ix, int32_t mode, const ann_launch_cfg* cfg);
 int ann_get_launch(const ann_index* ix, int32_t mode, ann_launch_cfg* out);
 
 /*
- * Times the candidate launch shapes on the given batch (device queries, as in
- * ann_search_ex) and keeps the fastest for `mode`.  Results are identical for
- * every shape (the arithmetic order is fixed); only speed differs.  The chosen
- * configuration is written to *best when not NULL.
+ * Times candidate launch shapes on the given batch (as for ann_search_ex;
+ * the outputs are written by every run) on the index stream and keeps the
+ * fastest for b->mode: lanes per row (16 / 32 / 64 where the mode supports
+ * them) x waves per query (1 / 2 / 4 / 8) with slots from the occupancy,
+ * then 3/4 and 1/2 of those slots for the best shape.  Each candidate runs
+ * twice and the second run is timed.  Shapes whose on-chip memory does not
+ * fit are skipped.  beam_buffer and beam_list keep their current values.
+ * Results are identical for every shape (the arithmetic order is fixed);
+ * only speed differs.  The chosen configuration is written to *best when not
+ * NULL.  Blocking; ANN_EBUDGET if no shape fits.
  */
 int ann_autotune(ann_index* ix, const ann_batch* b, ann_launch_cfg* best);
+
+/* ---- captured batches (HIP graphs) ---------------------------------------- */
+
+/*
+ * A plan records one batch shape as a HIP graph: the same search as
+ * ann_search_ex, with the buffers of `b` fixed (queries, per-query k / ef
+ * arrays, outputs) and the number of queries of each replay read from
+ * device memory at *nq_dev when the replay runs (values outside [0, b->nq]
+ * are clamped to it).  The caller refills the fixed buffers and *nq_dev on
+ * the device between replays; a serving loop then costs one graph launch per
+ * batch and no host-side argument work.  For callers that replay the same
+ * batch shape many times (the paper's one-query-at-a-time search, Section 3,
+ * batched for a GPU).
+ *   b        as for ann_search_ex; b->nq is the capacity (>= 1); the launch
+ *            shape is the index's current one for b->mode (ann_set_launch,
+ *            ann_autotune) and stays fixed in the plan
+ *   nq_dev   device i32: the batch size of each replay
+ *   out      the plan.  It owns its own workspace (visited bitsets, beam
+ *            lists), so replays never share scratch memory with other calls;
+ *            replays of one plan run one after the other on the device
+ *            whatever streams they use.
+ * ann_plan_launch replays the graph on `stream` (NULL: the index stream,
+ * and the call waits).  ann_plan_info gives the recorded launch shape (slots
+ * resolved).  ann_plan_free waits for the last replay and frees the plan;
+ * the index must outlive its plans.  Results equal ann_search_ex's for the
+ * same queries bit for bit.  Errors as for ann_search_ex.
+ */
+typedef struct ann_plan ann_plan;
+int ann_plan_create(const ann_index* ix, const ann_batch* b, const int32_t* nq_dev, ann_plan** out);
+int ann_plan_launch(ann_plan* plan, void* stream);
+int ann_plan_info(const ann_plan* plan, ann_launch_cfg* out);
+int ann_plan_free(ann_plan* plan);
 
 /* ---- exact search on matrix cores ---------------------------------------- */
 
@@ -288,7 +332,9 @@ int ann_autotune(ann_index* ix, const ann_batch* b, ann_launch_cfg* best);
  *                  difference between the MFMA and fixed-order sums), else 0
  * 1 <= k <= 48.  Needs x_f32.  Asynchronous on `stream` (NULL: the index
  * stream, blocking).  Uses a scratch buffer the index keeps (grown on
- * demand); calls on one index are serialized by the library.
+ * demand): the kernels of calls on one index run one call after the other
+ * on the device, whatever streams the calls use (each call's stream waits
+ * for an event recorded after the previous call's kernels).
  */
 int ann_bruteforce(const ann_index* ix, const float* queries, int64_t nq, int32_t k,
                    int64_t* out_ids, float* out_dists, int32_t* out_certified, void* stream);
@@ -388,7 +434,7 @@ int ann_encode_fp8(const float* X, int64_t n, int32_t d, uint8_t* out_codes, flo
 
 /*
  * An inverted-file index, the index family the paper names beside graphs
- * (Section 1) and plans to add (Section 5).  The coarse quantizer is a set of
+ * (Section 1) and plans to add (Section 4, Conclusions and Future Work).  The coarse quantizer is a set of
  * nlist FP32 centroids (k-means over whole vectors: ann_ivf_train below);
  * list l holds the rows whose nearest centroid is l.  The IVF index searches
  * the rows (or PQ codes) of an existing ann_index, which must outlive it; it

@@ -19,7 +19,7 @@
 //  * the Identity quantizer (Section 2), plus reduced-precision storage
 //    copies (FP16, BF16, FP8-E4M3 with a per-vector scale);
 //  * an inverted-file (IVF) index over a k-means coarse quantizer, the index
-//    family Section 1 names beside graphs and Section 5 plans to add.
+//    family Section 1 names beside graphs and Section 4 (Conclusions and Future Work) plans to add.
 //
 // Distances are "keys", smaller is better: squared L2, or the negated inner
 // product.  Two evaluation modes exist:
@@ -976,7 +976,7 @@ void or_pq_encode(const float* X, int64_t n, int d, const float* cb, int m, int 
 // --- IVF: inverted lists over a coarse quantizer ------------------------------
 //
 // The paper names IVF (Section 1) as one of the index families an ANN library
-// offers, and plans more index types (Section 5).  The coarse quantizer is
+// offers, and plans more index types (Section 4, Conclusions and Future Work).  The coarse quantizer is
 // k-means over the whole vector (lloyd above on a sample, L2), every row
 // belongs to the list of its EXACT nearest centroid, and a query scans the
 // lists of its nprobe nearest centroids.

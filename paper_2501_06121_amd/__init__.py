@@ -95,6 +95,10 @@ SIGNATURES = {
     "ann_set_launch": ([P, I32, P], C.c_int),
     "ann_get_launch": ([P, I32, P], C.c_int),
     "ann_autotune": ([P, P, P], C.c_int),
+    "ann_plan_create": ([P, P, P, P], C.c_int),
+    "ann_plan_launch": ([P, P], C.c_int),
+    "ann_plan_info": ([P, P], C.c_int),
+    "ann_plan_free": ([P], C.c_int),
     "ann_bruteforce": ([P, P, I64, I32, P, P, P, P], C.c_int),
     "ann_pq_train": ([P, I64, I32, P, I64, P, I32, I32, I32, P, P, P], C.c_int),
     "ann_pq_encode": ([P, I64, I32, P, I32, I32, P, P], C.c_int),
@@ -368,6 +372,70 @@ def ann_autotune(index, mode="f32", queries=None, sparse=None, k=10, ef=64, rera
     return {"slots": cfg.slots, "lanes_per_row": cfg.lanes_per_row,
             "waves_per_query": cfg.waves_per_query, "beam_buffer": cfg.beam_buffer,
             "beam_list": cfg.beam_list}
+
+
+class Plan:
+    """A captured batch (ann_plan_*): fixed device buffers for up to
+    `capacity` queries; refill ``queries`` (and ``k`` / ``ef`` when per-query)
+    in place, then ``launch(nq)`` replays the graph for the first nq."""
+
+    def __init__(self, index, mode, capacity, k=10, ef=64, rerank=0, k_max=None, ef_max=None,
+                 per_query=False, device="cuda:0"):
+        torch = _torch()
+        self.index = index
+        d = index.d
+        self.queries = torch.zeros((capacity, d), dtype=torch.float32, device=device)
+        self.nq = torch.zeros((1,), dtype=torch.int32, device=device)
+        k_max = int(k_max if k_max is not None else k)
+        ef_max = int(ef_max if ef_max is not None else ef)
+        self.k = torch.full((capacity,), int(k), dtype=torch.int32, device=device) if per_query else None
+        self.ef = torch.full((capacity,), int(ef), dtype=torch.int32, device=device) if per_query else None
+        self.ids = torch.empty((capacity, k_max), dtype=torch.int64, device=device)
+        self.dists = torch.empty((capacity, k_max), dtype=torch.float32, device=device)
+        self.status = torch.empty((capacity,), dtype=torch.int32, device=device)
+        self.stats = torch.empty((capacity, 4), dtype=torch.int32, device=device)
+        b = AnnBatch()
+        b.mode = MODE[mode] if isinstance(mode, str) else int(mode)
+        b.rerank = int(rerank)
+        b.nq = int(capacity)
+        b.queries = _dptr(self.queries)
+        b.k, b.ef = _dptr(self.k), _dptr(self.ef)
+        b.k_all, b.ef_all, b.k_max, b.ef_max = int(k), int(ef), k_max, ef_max
+        b.out_ids, b.out_dists = _dptr(self.ids), _dptr(self.dists)
+        b.out_status, b.out_stats = _dptr(self.status), _dptr(self.stats)
+        self.handle = P()
+        torch.cuda.synchronize()
+        _check(lib().ann_plan_create(index.handle, C.byref(b), _dptr(self.nq), C.byref(self.handle)))
+
+    def launch(self, nq=None, stream=None):
+        """Set the batch size on the device (on `stream`) and replay."""
+        torch = _torch()
+        if nq is not None:
+            if stream is None:
+                self.nq.fill_(int(nq))
+                torch.cuda.current_stream().synchronize()
+            else:
+                with torch.cuda.stream(stream):
+                    self.nq.fill_(int(nq))
+        _check(lib().ann_plan_launch(self.handle, _stream_handle(stream)))
+
+    def info(self):
+        cfg = AnnLaunchCfg()
+        _check(lib().ann_plan_info(self.handle, C.byref(cfg)))
+        return {"slots": cfg.slots, "lanes_per_row": cfg.lanes_per_row,
+                "waves_per_query": cfg.waves_per_query, "beam_buffer": cfg.beam_buffer,
+                "beam_list": cfg.beam_list}
+
+    def close(self):
+        if self.handle:
+            lib().ann_plan_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def ann_bruteforce(index, queries, k, stream=None):

@@ -232,6 +232,8 @@ int make_params(const ann_index* ix, const ann_batch* b, SearchParams* P) {
     P->rows = mode == ANN_MODE_F32 ? (const void*)ix->x_f32
             : mode == ANN_MODE_F16 ? (const void*)ix->x_f16
             : mode == ANN_MODE_BF16 ? (const void*)ix->x_bf16 : (const void*)ix->x_fp8;
+  } else if (mode == ANN_MODE_PQ) {
+    P->lanes_per_row = cfg.lanes_per_row ? cfg.lanes_per_row : 16;
   } else {
     P->lanes_per_row = 64;
   }
@@ -471,6 +473,7 @@ int ann_index_free(ann_index* ix) {
   hipDeviceSynchronize();
   ix->ws.release();
   if (ix->bf_scratch) (void)hipFree(ix->bf_scratch);
+  if (ix->bf_done) (void)hipEventDestroy(ix->bf_done);
   void* ptrs[] = {ix->adj0, ix->upper_off, ix->upper_adj, ix->x_f32, ix->x_f16, ix->x_bf16,
                   ix->x_fp8, ix->fp8_scale, ix->pq_cb, ix->pq_codes, ix->sp_ptr, ix->sp_ids,
                   ix->sp_vals};
@@ -550,8 +553,11 @@ int ann_set_launch(ann_index* ix, int32_t mode, const ann_launch_cfg* cfg) {
     return fail(ANN_EINVAL, "beam_buffer must be 0, -1 or in [64, 4096]");
   if (cfg->beam_list != ANN_BEAM_AUTO && cfg->beam_list != ANN_BEAM_LDS && cfg->beam_list != ANN_BEAM_HBM)
     return fail(ANN_EINVAL, "beam_list must be ANN_BEAM_AUTO, ANN_BEAM_LDS or ANN_BEAM_HBM");
-  if (cfg->lanes_per_row != 0) {
-    if (!is_dense(mode)) return fail(ANN_EINVAL, "lanes_per_row applies to dense modes");
+  if (cfg->lanes_per_row != 0 && mode == ANN_MODE_PQ) {
+    if (cfg->lanes_per_row != 16 && cfg->lanes_per_row != 32 && cfg->lanes_per_row != 64)
+      return fail(ANN_EINVAL, "PQ takes 16, 32 or 64 lanes per candidate");
+  } else if (cfg->lanes_per_row != 0) {
+    if (!is_dense(mode)) return fail(ANN_EINVAL, "lanes_per_row applies to dense and PQ modes");
     if (!dense_shape_supported(mode, ix->d * elem_bytes(mode) / 16, cfg->lanes_per_row))
       return fail(ANN_EBUDGET, "lanes_per_row %d not supported for d=%d", cfg->lanes_per_row, ix->d);
   }
@@ -565,6 +571,7 @@ int ann_get_launch(const ann_index* ix, int32_t mode, ann_launch_cfg* out) {
   if (mode < 0 || mode > ANN_MODE_SPARSE) return fail(ANN_EINVAL, "unknown mode");
   *out = ix->cfg[mode];
   if (out->lanes_per_row == 0 && is_dense(mode)) out->lanes_per_row = default_lanes(mode, ix->d);
+  if (out->lanes_per_row == 0 && mode == ANN_MODE_PQ) out->lanes_per_row = 16;
   return ANN_OK;
 }
 
@@ -574,39 +581,82 @@ int ann_autotune(ann_index* ix, const ann_batch* b, ann_launch_cfg* best) {
   int rc = make_params(ix, b, &P);
   if (rc) return rc;
   if (b->nq == 0) return fail(ANN_EINVAL, "autotune needs a non-empty batch");
-  std::vector<ann_launch_cfg> cands;
-  std::vector<int> lanes = is_dense(b->mode) ? std::vector<int>{16, 32, 64} : std::vector<int>{0};
-  for (int L : lanes) {
-    if (L && !dense_shape_supported(b->mode, P.nchunks, L)) continue;
-    for (int nw : {1, 2, 4, 8})
-      for (int mult : {1, 2, 4, 8, 16}) cands.push_back(ann_launch_cfg{ix->cu_count * mult, L, nw, ix->cfg[b->mode].beam_buffer,
-                                        ix->cfg[b->mode].beam_list});
-  }
+  const int mode = b->mode;
   std::lock_guard<std::mutex> lock(ix->mu);
-  hipEvent_t e0, e1;
-  HIP_OR_RETURN(hipEventCreate(&e0), "hipEventCreate");
-  HIP_OR_RETURN(hipEventCreate(&e1), "hipEventCreate");
-  float best_ms = 1e30f;
-  ann_launch_cfg pick = ix->cfg[b->mode];
-  for (const ann_launch_cfg& c : cands) {
-    SearchParams Q = P;
-    if (c.lanes_per_row) Q.lanes_per_row = c.lanes_per_row;
-    Q.waves_per_query = c.waves_per_query;
-    if (lds_bytes(Q) > ix->lds_limit) continue;
-    float ms = 0.f;
-    for (int rep = 0; rep < 2; ++rep) {  // first run warms caches
-      HIP_OR_RETURN(hipEventRecord(e0, ix->stream), "hipEventRecord");
-      rc = run_batch(ix, ix->ws, Q, c.slots, ix->stream);
-      if (rc) { hipEventDestroy(e0); hipEventDestroy(e1); return rc; }
-      HIP_OR_RETURN(hipEventRecord(e1, ix->stream), "hipEventRecord");
-      HIP_OR_RETURN(hipEventSynchronize(e1), "autotune run");
-      HIP_OR_RETURN(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+  // events and the configuration under test are restored on every exit
+  struct Guard {
+    ann_index* ix;
+    int mode;
+    ann_launch_cfg saved;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Guard() {
+      ix->cfg[mode] = saved;
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
     }
-    if (ms < best_ms) { best_ms = ms; pick = c; }
+  } g{ix, mode, ix->cfg[mode]};
+  HIP_OR_RETURN(hipSetDevice(ix->device), "hipSetDevice");
+  HIP_OR_RETURN(hipEventCreate(&g.e0), "hipEventCreate");
+  HIP_OR_RETURN(hipEventCreate(&g.e1), "hipEventCreate");
+  // one warm-up run (caches, workspace growth), then one timed run
+  auto time_cfg = [&](const ann_launch_cfg& c, float* ms) -> int {
+    ix->cfg[mode] = c;
+    SearchParams Q;
+    int r = make_params(ix, b, &Q);
+    if (r) return r;
+    for (int rep = 0; rep < 2; ++rep) {
+      HIP_OR_RETURN(hipEventRecord(g.e0, ix->stream), "hipEventRecord");
+      r = run_batch(ix, ix->ws, Q, c.slots, ix->stream);
+      if (r) return r;
+      HIP_OR_RETURN(hipEventRecord(g.e1, ix->stream), "hipEventRecord");
+      HIP_OR_RETURN(hipEventSynchronize(g.e1), "autotune run");
+      HIP_OR_RETURN(hipEventElapsedTime(ms, g.e0, g.e1), "hipEventElapsedTime");
+    }
+    return ANN_OK;
+  };
+  std::vector<int> lanes;
+  if (is_dense(mode)) {
+    for (int L : {16, 32, 64})
+      if (dense_shape_supported(mode, P.nchunks, L)) lanes.push_back(L);
+  } else if (mode == ANN_MODE_PQ) {
+    lanes = {16, 32, 64};
+  } else {
+    lanes = {0};
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  ix->cfg[b->mode] = pick;
+  float best_ms = 1e30f;
+  ann_launch_cfg pick = g.saved;
+  // 1. lanes per row x waves per query, slots from the occupancy
+  for (int L : lanes) {
+    for (int nw : {1, 2, 4, 8}) {
+      ann_launch_cfg c = g.saved;
+      c.slots = 0;
+      c.lanes_per_row = L;
+      c.waves_per_query = nw;
+      float ms = 0.f;
+      rc = time_cfg(c, &ms);
+      if (rc == ANN_EBUDGET) continue;     // this shape does not fit on chip
+      if (rc) return rc;
+      if (ms < best_ms) { best_ms = ms; pick = c; }
+    }
+  }
+  if (best_ms >= 1e30f) return fail(ANN_EBUDGET, "no launch shape fits this batch");
+  // 2. fewer slots than the occupancy allows (less contention for the
+  //    caches and the memory system), for the best shape
+  {
+    ix->cfg[mode] = pick;
+    SearchParams Q;
+    if ((rc = make_params(ix, b, &Q))) return rc;
+    const int64_t full = pick_slots(ix, Q, 0);
+    for (int64_t sl : {full * 3 / 4, full / 2}) {
+      if (sl < 1) continue;
+      ann_launch_cfg c = pick;
+      c.slots = (int32_t)sl;
+      float ms = 0.f;
+      if ((rc = time_cfg(c, &ms))) return rc;
+      if (ms < best_ms) { best_ms = ms; pick = c; }
+    }
+  }
+  g.saved = pick;   // the guard installs the winner
   if (best) *best = pick;
   return ANN_OK;
 }

@@ -456,9 +456,12 @@ extern "C" int ann_bruteforce(const ann_index* cix, const float* queries, int64_
   hipStream_t st = stream ? (hipStream_t)stream : ix->stream;
   const int nranges = bf_ranges(ix->n, nq, ix->cu_count > 0 ? ix->cu_count : 256);
   const size_t need = bruteforce_scratch_bytes(ix->n, nq, nranges);
+  if (!ix->bf_done)
+    HIP_OR_RETURN(hipEventCreateWithFlags(&ix->bf_done, hipEventDisableTiming), "hipEventCreate");
   if (ix->bf_scratch_bytes < need) {
     if (ix->bf_scratch) {
-      HIP_OR_RETURN(hipStreamSynchronize(st), "hipStreamSynchronize");
+      // the previous call (on whatever stream) is done with the old buffer
+      if (ix->bf_used) HIP_OR_RETURN(hipEventSynchronize(ix->bf_done), "hipEventSynchronize");
       (void)hipFree(ix->bf_scratch);
       ix->bf_scratch = nullptr;
       ix->bf_scratch_bytes = 0;
@@ -467,6 +470,9 @@ extern "C" int ann_bruteforce(const ann_index* cix, const float* queries, int64_
     ix->bf_scratch_bytes = need;
     ix->bf_norms_ready = false;
   }
+  // the scratch is shared by every call on this index: this call's kernels
+  // start after the previous call's, whatever streams the two use
+  if (ix->bf_used) HIP_OR_RETURN(hipStreamWaitEvent(st, ix->bf_done, 0), "hipStreamWaitEvent");
   char* base = (char*)ix->bf_scratch;
   float* x2 = (float*)base;
   float* ckey = (float*)(base + (((size_t)ix->n * 4 + 255) & ~size_t(255)));
@@ -496,6 +502,8 @@ extern "C" int ann_bruteforce(const ann_index* cix, const float* queries, int64_
   f.out_ids = out_ids; f.out_dists = out_dists; f.out_certified = out_certified;
   hipLaunchKernelGGL(bf_finish, dim3((unsigned)nq), dim3(64), 0, st, f);
   HIP_OR_RETURN(hipGetLastError(), "bf_finish launch");
+  HIP_OR_RETURN(hipEventRecord(ix->bf_done, st), "hipEventRecord");
+  ix->bf_used = true;
   if (!stream) HIP_OR_RETURN(hipStreamSynchronize(st), "brute force");
   return ANN_OK;
 }

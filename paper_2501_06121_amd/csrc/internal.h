@@ -73,6 +73,8 @@ struct ann_index {
   void* bf_scratch = nullptr;        // brute-force candidates and row norms
   size_t bf_scratch_bytes = 0;
   bool bf_norms_ready = false;
+  hipEvent_t bf_done = nullptr;      // recorded after the last brute-force call's kernels
+  bool bf_used = false;
   ann_launch_cfg cfg[6] = {};
   std::mutex mu;
   ann::Workspace ws;                 // used by ann_search / ann_search_ex

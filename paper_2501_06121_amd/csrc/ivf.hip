@@ -1,6 +1,6 @@
 // IVF index on the device: inverted lists over a k-means coarse quantizer,
 // the index family the paper names beside graphs (Section 1) and plans to add
-// (Section 5), searched with the same representations and keys as the HNSW
+// (Section 4, Conclusions and Future Work), searched with the same representations and keys as the HNSW
 // path (FP32 / FP16 / BF16 / FP8 rows, PQ codes, optional FP32 rerank).
 //
 // A batch runs two kernels (plus, for the dense modes, a choice of scan):
@@ -503,7 +503,7 @@ const void* scan_symbol(const SearchParams& p) {
     case MODE_F16: return scan_dense<MODE_F16, SH>(L, cpl);
     case MODE_BF16: return scan_dense<MODE_BF16, SH>(L, cpl);
     case MODE_FP8: return scan_dense<MODE_FP8, SH>(L, cpl);
-    case MODE_PQ: return SH ? nullptr : scan_sym<PQ, false>();
+    case MODE_PQ: return SH ? nullptr : scan_sym<PQ<16>, false>();
   }
   return nullptr;
 }

@@ -1,6 +1,6 @@
 // Construction of the IVF index on the device: k-means training of the coarse
 // centroids and the assignment of every row to its list.  The paper names the
-// IVF family (Section 1) and plans more index types (Section 5); the coarse
+// IVF family (Section 1) and plans more index types (Section 4, Conclusions and Future Work); the coarse
 // quantizer is Lloyd's k-means over whole vectors, the procedure the PQ
 // training applies per subspace (Section 2 and its citation, Jegou et al.).
 //

@@ -137,8 +137,12 @@ struct Lds {
   int32_t* ctl;      // [16] values wave 0 publishes to the other waves
 };
 
+// CTL_M and CTL_M_ODD carry an expansion's candidate counts, alternating by
+// the parity of the expansion: a wave that has not yet read the count of one
+// expansion (no barrier follows an expansion without new entries) never sees
+// it overwritten by the next one.
 enum { CTL_QUERY = 0, CTL_M = 1, CTL_W = 2, CTL_HINT = 3, CTL_VISITED = 4, CTL_VLOG = 5,
-       CTL_VLOG_OVF = 6, CTL_FLUSH = 7, CTL_R0 = 8 };
+       CTL_VLOG_OVF = 6, CTL_FLUSH = 7, CTL_R0 = 8, CTL_M_ODD = 9 };
 
 __device__ Lds carve(char* base, const SearchParams& p) {
   Lds s;
@@ -322,10 +326,23 @@ struct Dense {
 };
 
 // ----------------------------------------------------------------------------
-// PQ asymmetric distance: LUT[m][j] in LDS, one lane per candidate.
+// PQ asymmetric distance: LUT[m][j] in LDS.  The key of a row is the fixed
+// fold of its per-subspace entries p[m] = LUT[m][code_m] (m < 64, +0 beyond
+// pq_m).  Two schedules give the same bits:
+//   - few candidates (an HNSW expansion, about 6 new rows): L lanes per
+//     candidate, lane j of a group holding the entries m = j + L v (one LDS
+//     lookup each); the fold levels s >= L run in registers, the levels
+//     s < L across the group's lanes;
+//   - long runs (a 64-row chunk of an IVF list): one lane per candidate, all
+//     64 entries and the whole fold in registers.
 // ----------------------------------------------------------------------------
 
+template <int L>
 struct PQ {
+  static constexpr int V = 64 / L;   // entries per lane
+  static constexpr int G = 64 / L;   // candidates per pass of the wave
+  static constexpr int U = 2;        // passes whose codes are in flight together
+
   __device__ __forceinline__ bool prep(const SearchParams& p, const Lds& s, int64_t q) {
     const int ds = p.pq_dsub;
     const int entries = p.pq_m * 256;
@@ -349,10 +366,9 @@ struct PQ {
     return true;
   }
 
-  __device__ __forceinline__ void score(const SearchParams& p, const Lds& s, int m) {
-    const int per = (m + num_waves() - 1) / num_waves();
-    const int ci = wave_id() * per + lane_id();
-    if (lane_id() < per && ci < m) {
+  // candidates s.cid[lo..hi) by the calling wave, one lane each
+  __device__ __forceinline__ void score_lanes(const SearchParams& p, const Lds& s, int lo, int hi) {
+    for (int ci = lo + lane_id(); ci < hi; ci += 64) {
       const int64_t r = s.cid[ci];
       const uint4* cp = (const uint4*)(p.pq_codes + (size_t)r * p.pq_stride);
       float part[64];
@@ -373,6 +389,56 @@ struct PQ {
         for (int v = 0; v < h; ++v) part[v] = part[v] + part[v + h];
       s.ckey[ci] = (p.metric == METRIC_IP) ? -part[0] : part[0];
     }
+  }
+
+  // candidates s.cid[lo..hi) by the calling wave, L lanes each
+  __device__ __forceinline__ void score_groups(const SearchParams& p, const Lds& s, int lo, int hi) {
+    const int lane = lane_id();
+    const int j = lane & (L - 1);
+    const int grp = lane / L;
+    for (int base = lo; base < hi; base += G * U) {
+      uint32_t code[U][V];
+      int rid[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int ci = base + u * G + grp;
+        rid[u] = (ci < hi) ? s.cid[ci] : -1;
+        const uint8_t* cp = p.pq_codes + (size_t)(rid[u] < 0 ? 0 : rid[u]) * p.pq_stride;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const int m = j + L * v;
+          code[u][v] = (rid[u] >= 0 && m < p.pq_m) ? (uint32_t)cp[m] : 0u;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (base + u * G >= hi) break;
+        float acc[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const int m = j + L * v;
+          acc[v] = (rid[u] >= 0 && m < p.pq_m) ? s.lut[m * 256 + (int)code[u][v]] : 0.0f;
+        }
+        // levels s = 32 .. L inside the lane, then s = L/2 .. 1 across the group
+#pragma unroll
+        for (int h = V / 2; h >= 1; h >>= 1)
+#pragma unroll
+          for (int v = 0; v < h; ++v) acc[v] = acc[v] + acc[v + h];
+        const float val = fold_lanes<L>(acc[0]);
+        const int ci = base + u * G + grp;
+        if (j == 0 && ci < hi) s.ckey[ci] = (p.metric == METRIC_IP) ? -val : val;
+      }
+    }
+  }
+
+  // keys of the m candidate ids in s.cid[] into s.ckey[]; the waves of the
+  // workgroup take contiguous shares
+  __device__ __forceinline__ void score(const SearchParams& p, const Lds& s, int m) {
+    const int per = (m + num_waves() - 1) / num_waves();
+    const int lo = wave_id() * per;
+    const int hi = lo + per < m ? lo + per : m;
+    if (hi - lo > 16) score_lanes(p, s, lo, hi);
+    else if (hi > lo) score_groups(p, s, lo, hi);
   }
 };
 
@@ -963,6 +1029,7 @@ __device__ __forceinline__ void run_query(const SearchParams& p, const Lds& s, P
     hint = pm < 0 ? w : from_buf ? pm : pm + 1;
     hint_b = pb < 0 ? wb : from_buf ? pb + 1 : pb;
     st.expansions += 1;
+    const int cm = (st.expansions & 1) ? CTL_M_ODD : CTL_M;
     if (wave == 0) {
       // neighbour list, visited bits (each bit set exactly once), compaction
       const int nb = (lane < p.M0) ? p.adj0[(size_t)c * p.M0 + lane] : -1;
@@ -975,7 +1042,7 @@ __device__ __forceinline__ void run_query(const SearchParams& p, const Lds& s, P
       const uint64_t mk = ballot(isnew);
       log_visited(p, slot, q, st, isnew, nb, mk);
       if (isnew) s.cid[mbcnt(mk)] = nb;
-      if (lane == 0) s.ctl[CTL_M] = __builtin_popcountll(mk);
+      if (lane == 0) s.ctl[cm] = __builtin_popcountll(mk);
     }
     __syncthreads();
     // every wave has read the entry: mark it (scans resume after it, and the
@@ -984,7 +1051,7 @@ __device__ __forceinline__ void run_query(const SearchParams& p, const Lds& s, P
       if (from_buf) s.bid[pb] = (uint32_t)c | kExpanded;
       else L.id[pm] = (uint32_t)c | kExpanded;
     }
-    const int m = s.ctl[CTL_M];
+    const int m = s.ctl[cm];
     if (m == 0) continue;
     pol.score(p, s, m);
     __syncthreads();
@@ -1016,13 +1083,13 @@ __device__ __forceinline__ void run_query(const SearchParams& p, const Lds& s, P
       wave_sync();
       if (keep) { s.ckey[rk] = kk; s.cid[rk] = (int32_t)ki; }
       if (lane == 0) {
-        s.ctl[CTL_M] = mnew;
+        s.ctl[cm] = mnew;
         s.ctl[CTL_FLUSH] = (buffered && wb + mnew > p.wbuf) ? 1 : 0;
         s.ctl[CTL_HINT] = 0x7FFFFFFF;
       }
     }
     __syncthreads();
-    const int mnew = s.ctl[CTL_M];
+    const int mnew = s.ctl[cm];
     if (mnew > 0) {
       if (!buffered) {
         w = merge_sorted<4>(L.key, L.id, w, ef, s.ckey, (const uint32_t*)s.cid, mnew, &s.ctl[CTL_R0],
@@ -1078,47 +1145,57 @@ __device__ __forceinline__ void run_query(const SearchParams& p, const Lds& s, P
     nres = R;
     const int nch = p.d / 4;   // FP32 chunks
     for (int i0 = 4 * wave; i0 < R; i0 += 4 * num_waves()) {
-      // four rows at a time, 64 lanes per row
-      uint4 raw[4][4];
+      // four rows at a time, 64 lanes per row; lane l takes chunks l + 64 t
+      // in ascending t (256 chunks, 1,024 floats, per round)
       int rid[4];
+      float acc[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         rid[u] = (i0 + u < R) ? (int)(L.id[i0 + u] & kIdMask) : -1;
+        acc[u] = 0.0f;
+      }
+      for (int tb = 0; tb < nch; tb += 256) {
+        uint4 raw[4][4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int g = lane + 64 * t;
-          raw[u][t] = (rid[u] >= 0 && g < nch)
-              ? *(const uint4*)(p.x_f32 + (size_t)rid[u] * p.d + (size_t)g * 4)
-              : make_uint4(0u, 0u, 0u, 0u);
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int g = tb + lane + 64 * t;
+            raw[u][t] = (rid[u] >= 0 && g < nch)
+                ? *(const uint4*)(p.x_f32 + (size_t)rid[u] * p.d + (size_t)g * 4)
+                : make_uint4(0u, 0u, 0u, 0u);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int g = tb + lane + 64 * t;
+            if (g < nch) {
+              const float* qc = s.q + g * 4;
+              if (p.metric == METRIC_IP) {
+                acc[u] = __builtin_fmaf(qc[0], __uint_as_float(raw[u][t].x), acc[u]);
+                acc[u] = __builtin_fmaf(qc[1], __uint_as_float(raw[u][t].y), acc[u]);
+                acc[u] = __builtin_fmaf(qc[2], __uint_as_float(raw[u][t].z), acc[u]);
+                acc[u] = __builtin_fmaf(qc[3], __uint_as_float(raw[u][t].w), acc[u]);
+              } else {
+                const float t0 = qc[0] - __uint_as_float(raw[u][t].x);
+                const float t1 = qc[1] - __uint_as_float(raw[u][t].y);
+                const float t2 = qc[2] - __uint_as_float(raw[u][t].z);
+                const float t3 = qc[3] - __uint_as_float(raw[u][t].w);
+                acc[u] = __builtin_fmaf(t0, t0, acc[u]);
+                acc[u] = __builtin_fmaf(t1, t1, acc[u]);
+                acc[u] = __builtin_fmaf(t2, t2, acc[u]);
+                acc[u] = __builtin_fmaf(t3, t3, acc[u]);
+              }
+            }
+          }
         }
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        float acc = 0.0f;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int g = lane + 64 * t;
-          if (g < nch) {
-            const float* qc = s.q + g * 4;
-            if (p.metric == METRIC_IP) {
-              acc = __builtin_fmaf(qc[0], __uint_as_float(raw[u][t].x), acc);
-              acc = __builtin_fmaf(qc[1], __uint_as_float(raw[u][t].y), acc);
-              acc = __builtin_fmaf(qc[2], __uint_as_float(raw[u][t].z), acc);
-              acc = __builtin_fmaf(qc[3], __uint_as_float(raw[u][t].w), acc);
-            } else {
-              const float t0 = qc[0] - __uint_as_float(raw[u][t].x);
-              const float t1 = qc[1] - __uint_as_float(raw[u][t].y);
-              const float t2 = qc[2] - __uint_as_float(raw[u][t].z);
-              const float t3 = qc[3] - __uint_as_float(raw[u][t].w);
-              acc = __builtin_fmaf(t0, t0, acc);
-              acc = __builtin_fmaf(t1, t1, acc);
-              acc = __builtin_fmaf(t2, t2, acc);
-              acc = __builtin_fmaf(t3, t3, acc);
-            }
-          }
-        }
-        acc = fold_lanes<64>(acc);
-        if (lane == 0 && rid[u] >= 0) s.rk[i0 + u] = (p.metric == METRIC_IP) ? -acc : acc;
+        const float v = fold_lanes<64>(acc[u]);
+        if (lane == 0 && rid[u] >= 0) s.rk[i0 + u] = (p.metric == METRIC_IP) ? -v : v;
       }
     }
     __syncthreads();
@@ -1187,7 +1264,12 @@ __global__ void __launch_bounds__(512) ANN_OCCUPANCY search_kernel(SearchParams 
   const Lds s = carve(lds_raw, p);
   Policy pol;
   const int slot = blockIdx.x;
-  const int64_t nq = p.nq_dev ? (int64_t)uniform_int(*p.nq_dev) : p.nq;
+  // a device-held batch size (captured launches) is clamped to the buffers' capacity p.nq
+  int64_t nq = p.nq;
+  if (p.nq_dev) {
+    const int64_t nd = (int64_t)uniform_int(*p.nq_dev);
+    nq = nd < 0 ? 0 : nd < p.nq ? nd : p.nq;
+  }
   while (true) {
     if (threadIdx.x == 0) s.ctl[CTL_QUERY] = atomicAdd(p.counter, 1);
     __syncthreads();

@@ -66,3 +66,29 @@ def test_bruteforce_rejects_bad_k(gmm10k):
             ann.ann_bruteforce(ix, torch.zeros((2, 128), device="cuda:0"), 49)
     finally:
         ix.close()
+
+
+def test_calls_on_two_streams_share_the_scratch_safely(gmm10k):
+    """Back-to-back asynchronous calls on two streams use the index's one
+    candidate buffer in turn: each result equals the oracle's exact scan."""
+    X, Q = gmm10k["X"], gmm10k["Q"]
+    ix = ann.ann_index_create(gmm10k["graph"], "l2", 128, x_f32=X)
+    try:
+        s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+        q1 = torch.from_numpy(Q[:64]).to("cuda:0")
+        q2 = torch.from_numpy(Q[64:]).to("cuda:0")
+        torch.cuda.synchronize()
+        outs = []
+        for rep in range(3):
+            outs.append(ann.ann_bruteforce(ix, q1, 10, stream=s1))
+            outs.append(ann.ann_bruteforce(ix, q2, 10, stream=s2))
+        torch.cuda.synchronize()
+    finally:
+        ix.close()
+    ref_ids, ref_k = oracle.bruteforce(oracle.dense_store(X, "l2"), X.shape[0], 10, Q=Q,
+                                       kmode="canon")
+    for j, (ids, d, cert) in enumerate(outs):
+        sl = slice(0, 64) if j % 2 == 0 else slice(64, None)
+        assert cert.cpu().numpy().all()
+        assert np.array_equal(ids.cpu().numpy(), ref_ids[sl]), j
+        assert np.array_equal(d.cpu().numpy(), ref_k[sl]), j

@@ -83,3 +83,17 @@ def test_bad_arguments():
     with pytest.raises(ann.AnnError) as e:
         ann.ann_ivf_group(np.array([0, 3, 1], np.int32), 3)
     assert e.value.code == ann.ANN_EINVAL
+
+
+def test_empty_cluster_reseed_worked_example():
+    """The hand-worked re-seed case of the CPU pins on 2-d rows (second
+    coordinate 0): after one iteration 5, 30, -10; after two 2.5, 30, -10."""
+    x = np.array([0.0, 0.0, 0.0, -10.0, 10.0, 30.0], np.float32)
+    X = np.stack([x, np.zeros(6, np.float32)], axis=1)
+    for iters, want in {1: [5.0, 30.0, -10.0], 2: [2.5, 30.0, -10.0]}.items():
+        cent, it = ann.ann_ivf_train(dev(X), dev(np.arange(6, dtype=np.int64)),
+                                     dev(np.array([0, 1, 2], np.int64)), 3, max_iter=iters)
+        torch.cuda.synchronize()
+        assert it == iters
+        c = cent.cpu().numpy()
+        assert c[:, 0].tolist() == want and not c[:, 1].any()

@@ -164,6 +164,30 @@ def test_pq_adc_bitexact(c1):
         ix.close()
 
 
+@pytest.mark.parametrize("m", [64, 48, 16])
+def test_pq_lane_groups_bitexact(v768, m):
+    """PQ on the 4,096 x 768 IP set with m = 64, 48 and 16 subspaces, scored
+    by 16, 32 and 64 lanes per candidate, with 1 and 2 waves per query (HNSW
+    expansions take the lane-group schedule, long candidate runs one lane per
+    row): ids, keys, visited counts and |W| equal the oracle's."""
+    X = v768["X"]
+    sample, init = synth.pq_sample(0, X.shape[0], X.shape[0], 256)
+    cb, _, _ = oracle.pq_train(X, m, 256, sample, init, max_iter=3)
+    codes = oracle.pq_encode(X, cb)
+    ix = ann.ann_index_create(v768["g"], "ip", X.shape[1], x_f32=X, pq_codebook=cb, pq_codes=codes)
+    try:
+        ref = oracle.hnsw_search(v768["g"], oracle.pq_store(cb, codes, "ip"), 10, 80, Q=v768["Q"],
+                                 rerank_f32=X, rerank=40)
+        for lanes in (16, 32, 64):
+            for waves in (1, 2):
+                say(f"pq m={m} lanes={lanes} waves={waves}")
+                ann.ann_set_launch(ix, "pq", lanes_per_row=lanes, waves_per_query=waves)
+                assert ann.ann_get_launch(ix, "pq")["lanes_per_row"] == lanes
+                assert_same(gpu(ix, "pq", v768["Q"], 10, 80, rerank=40), ref)
+    finally:
+        ix.close()
+
+
 def test_sparse_bitexact(sparse_small):
     s = sparse_small
     ix = ann.ann_index_create(s["graph"], "ip", s["vocab"], sp_indptr=s["indptr"], sp_ids=s["ids"],
@@ -181,6 +205,64 @@ def test_sparse_bitexact(sparse_small):
             assert_same(got, ref)
     finally:
         ix.close()
+
+
+def test_sparse_query_above_256_terms_is_truncated_and_flagged(sparse_small):
+    """A sparse query keeps at most 256 terms on the device: longer ones are
+    searched with their first 256 (by position) and flagged with status bit 2;
+    exactly 256 terms is searched whole."""
+    s = sparse_small
+    rng = np.random.default_rng(21)
+    lens = [256, 257, 300, 40]
+    rows = [np.sort(rng.choice(s["vocab"], size=m, replace=False)).astype(np.uint16) for m in lens]
+    vals = [rng.lognormal(0.0, 0.5, size=m).astype(np.float32) for m in lens]
+    qp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    qi = np.concatenate(rows)
+    qv = np.concatenate(vals)
+    # what the device searches: each query cut to its first 256 terms
+    cut = [min(m, 256) for m in lens]
+    tp = np.concatenate([[0], np.cumsum(cut)]).astype(np.int64)
+    ti = np.concatenate([r[:c] for r, c in zip(rows, cut)])
+    tv = np.concatenate([v[:c] for v, c in zip(vals, cut)])
+    ix = ann.ann_index_create(s["graph"], "ip", s["vocab"], sp_indptr=s["indptr"], sp_ids=s["ids"],
+                              sp_vals=s["vals"])
+    try:
+        sq = (torch.from_numpy(qp).to(DEV), torch.from_numpy(qi.view(np.int16)).to(DEV),
+              torch.from_numpy(qv).to(DEV))
+        r = ann.ann_search_ex(ix, "sparse", sparse=sq, k=10, ef=64, want_stats=True)
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in r.items()}
+    finally:
+        ix.close()
+    assert got["status"].tolist() == [0, 2, 2, 0]
+    ref = oracle.hnsw_search(s["graph"], s["store"], 10, 64, sparse_q=(tp, ti, tv))
+    assert np.array_equal(got["ids"], ref["ids"])
+    assert np.array_equal(got["dists"], ref["keys"])
+    # the untruncated 300-term query ranks differently in the oracle
+    full = oracle.hnsw_search(s["graph"], s["store"], 10, 64, sparse_q=(qp, qi, qv))
+    assert not np.array_equal(full["keys"][2], ref["keys"][2])
+
+
+@pytest.mark.parametrize("d,metric", [(1536, "l2"), (2048, "ip")])
+def test_rerank_above_1024_dimensions(d, metric):
+    """FP32 rerank of rows wider than 1,024 floats (more than one round of
+    256 chunks per lane): FP16 traversal + rerank of 30 equals the oracle."""
+    n, nq = 1200, 16
+    X = synth.gaussian_mixture(31, n, d, 8, 0.3)
+    Q = synth.gaussian_mixture(31, nq, d, 8, 0.3, which="queries")
+    if metric == "ip":
+        X /= np.linalg.norm(X, axis=1, keepdims=True)
+        Q /= np.linalg.norm(Q, axis=1, keepdims=True)
+    g = oracle.hnsw_build(X, metric, 8, 32, synth.level_uniforms(31, n))
+    say(f"rerank at d={d} {metric}")
+    ix = ann.ann_index_create(g, metric, d, x_f32=X, x_f16=oracle.to_f16(X))
+    try:
+        got = gpu(ix, "f16", Q, 10, 40, rerank=30)
+    finally:
+        ix.close()
+    ref = oracle.hnsw_search(g, oracle.dense_store(oracle.to_f16(X), metric, "f16"), 10, 40, Q=Q,
+                             rerank_f32=X, rerank=30)
+    assert_same(got, ref)
 
 
 def test_edge_cases(c1):

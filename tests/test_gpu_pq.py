@@ -78,3 +78,16 @@ def test_small_codebooks_and_ragged_rows():
         assert np.array_equal(cb.view(np.uint32), ref_cb.view(np.uint32))
         codes = ann.ann_pq_encode(dev(X), dev(ref_cb)).cpu().numpy()
         assert np.array_equal(codes, oracle.pq_encode(X, ref_cb))
+
+
+def test_empty_cluster_reseed_worked_example():
+    """The hand-worked re-seed case of the CPU pins (one dimension, points
+    0 0 0 -10 10 30, three centroids at 0): after one iteration 5, 30, -10;
+    after two 2.5, 30, -10."""
+    X = np.array([0.0, 0.0, 0.0, -10.0, 10.0, 30.0], np.float32)[:, None]
+    for iters, want in {1: [5.0, 30.0, -10.0], 2: [2.5, 30.0, -10.0]}.items():
+        cb, it = ann.ann_pq_train(dev(X), dev(np.arange(6, dtype=np.int64)),
+                                  dev(np.array([0, 1, 2], np.int64)), 1, 3, iters)
+        torch.cuda.synchronize()
+        assert it == iters
+        assert cb.cpu().numpy()[0, :, 0].tolist() == want
