@@ -56,7 +56,7 @@ extern "C" {
 #define ANN_ENODEV 2   /* no usable GPU / bad device ordinal */
 #define ANN_ENOMEM 3   /* device allocation failed */
 #define ANN_EBUDGET 4  /* request beyond a compiled or configured capacity */
-#define ANN_EFORMAT 5  /* malformed index description (graph or arrays) */
+#define ANN_EFORMAT 5  /* malformed index description or index file (graph, arrays, checksums) */
 #define ANN_EHIP 6     /* HIP runtime error; text in ann_last_error() */
 #define ANN_EUNSUP 7   /* the index lacks the arrays the requested mode needs */
 #define ANN_EAGAIN 8   /* serving queue full, try again later */
@@ -145,15 +145,82 @@ int ann_index_create(const ann_index_desc* desc, int device, ann_index** out);
 /* Frees the index and its device memory (waits for the device first). */
 int ann_index_free(ann_index* ix);
 
-typedef struct ann_index_info {
+/* What an index (or an index file) holds. */
+typedef struct ann_info {
   int64_t n;
   int32_t d, metric, M, M0, max_level, entry_point;
   int32_t modes;       /* bit (1 << mode) set for every searchable mode */
-  int32_t device;
-  int64_t device_bytes;
-} ann_index_info;
+  int32_t device;      /* -1 for a file */
+  int64_t device_bytes;  /* device memory of the index (of a file: of its arrays) */
+} ann_info;
 
-int ann_index_info_get(const ann_index* ix, ann_index_info* out);
+int ann_index_info(const ann_index* ix, ann_info* out);
+/* The same, under the name of an earlier version of this header. */
+int ann_index_info_get(const ann_index* ix, ann_info* out);
+
+/* ---- index files --------------------------------------------------------- */
+
+/*
+ * One file holds everything an ann_index_desc describes: the graph and every
+ * stored representation (the Dataset component of the paper, Section 2 and
+ * Figure 1: the data an index is built over and searched with).  Version 1,
+ * little-endian:
+ *
+ *   header, bytes 0..127
+ *      0  u8[8]  magic "ANNINDEX"
+ *      8  u32    version (1)
+ *     12  u32    section count S (1..14)
+ *     16  i64    n
+ *     24  i32    d                 28  i32  metric
+ *     32  i32    M                 36  i32  M0
+ *     40  i32    max_level         44  i32  entry_point
+ *     48  i64    n_upper_lists
+ *     56  i32    pq_m (0: no PQ)   60  i32  pq_ksub (0 or 256)
+ *     64  i64    nnz (sparse nonzeros; 0: no sparse rows)
+ *     72  u8[52] zero
+ *    124  u32    CRC-32 of bytes 0..123
+ *   section table, bytes 128 .. 128 + 32 S, one entry per section:
+ *      0  u32 id   4  u32 CRC-32 of the section's bytes
+ *      8  u64 offset (from the start of the file)   16  u64 size   24  u64 zero
+ *   then a u32 CRC-32 of the table's 32 S bytes.
+ *   sections, in ascending id, each starting at the first multiple of 64 at
+ *   or after the end of what precedes it (zero bytes in between); the file
+ *   ends with the last section.
+ *
+ *   id  section       type, size            id  section       type, size
+ *    1  levels        u8[n]                  8  x_fp8         u8[n][d]
+ *    2  adj0          i32[n][M0]             9  fp8_scale     f32[n]
+ *    3  upper_off     i32[n]                10  pq_codebook   f32[pq_m][256][d/pq_m]
+ *    4  upper_adj     i32[n_upper_lists][M] 11  pq_codes      u8[n][pq_m]
+ *    5  x_f32         f32[n][d]             12  sp_indptr     i64[n + 1]
+ *    6  x_f16         u16[n][d]             13  sp_ids        u16[nnz]
+ *    7  x_bf16        u16[n][d]             14  sp_vals       f32[nnz]
+ *   Sections 1-3 are required, 4 iff n_upper_lists > 0; 8 and 9 go together,
+ *   10 and 11 iff pq_m > 0, 12-14 iff nnz > 0.  The arrays have the layout
+ *   and meaning of the ann_index_desc fields of the same names.  CRC-32 is
+ *   the IEEE 802.3 one (reflected polynomial 0xEDB88320, initial value and
+ *   final xor 0xFFFFFFFF; "123456789" gives 0xCBF43926).
+ *
+ * ann_index_file_info reads and checks a file on the host only (no GPU):
+ * magic, version, every CRC, the section table (known ids, ascending,
+ * aligned, non-overlapping, inside the file, the sizes above, the required
+ * and paired sections) and then every check of ann_index_create on the
+ * arrays.  Returns ANN_EFORMAT with the reason in ann_last_error() for a
+ * file that fails any of them (corrupt, truncated, another version),
+ * ANN_EINVAL if the file cannot be opened.  On success *out describes the
+ * file (device = -1).
+ *
+ * ann_index_load does the same checks, then ann_index_create with the file's
+ * arrays on GPU `device` (ANN_ENODEV without one).  The file is mapped, not
+ * copied, on the host.
+ *
+ * ann_index_save writes the arrays of a description to `path` in this
+ * format (after the checks of ann_index_create; ANN_EINVAL if the file
+ * cannot be written).  Host only.
+ */
+int ann_index_file_info(const char* path, ann_info* out);
+int ann_index_load(const char* path, int device, ann_index** out);
+int ann_index_save(const ann_index_desc* desc, const char* path);
 
 /* ---- search ------------------------------------------------------------ */
 

@@ -88,7 +88,11 @@ class AnnIvfBatch(C.Structure):
 SIGNATURES = {
     "ann_index_create": ([P, C.c_int, P], C.c_int),
     "ann_index_free": ([P], C.c_int),
+    "ann_index_info": ([P, P], C.c_int),
     "ann_index_info_get": ([P, P], C.c_int),
+    "ann_index_file_info": ([C.c_char_p, P], C.c_int),
+    "ann_index_load": ([C.c_char_p, C.c_int, P], C.c_int),
+    "ann_index_save": ([P, C.c_char_p], C.c_int),
     "ann_search": ([P, P, I64, I32, I32, P, P], C.c_int),
     "ann_search_ex": ([P, P, P], C.c_int),
     "ann_search_sparse": ([P, P, P, P, I64, I32, I32, P, P], C.c_int),
@@ -218,15 +222,13 @@ class Index:
 
     def info(self):
         out = AnnIndexInfo()
-        _check(lib().ann_index_info_get(self.handle, C.byref(out)))
+        _check(lib().ann_index_info(self.handle, C.byref(out)))
         return {f: getattr(out, f) for f, _ in AnnIndexInfo._fields_}
 
 
-def ann_index_create(graph, metric, d, x_f32=None, x_f16=None, x_bf16=None, x_fp8=None,
-                     fp8_scale=None, pq_codebook=None, pq_codes=None, sp_indptr=None,
-                     sp_ids=None, sp_vals=None, device=0):
-    """Copy host arrays to the device.  `graph` has the attributes n, M, M0,
-    max_level, entry, levels, adj0, upper_off, upper_adj (exchange layout)."""
+def _desc(graph, metric, d, x_f32=None, x_f16=None, x_bf16=None, x_fp8=None, fp8_scale=None,
+          pq_codebook=None, pq_codes=None, sp_indptr=None, sp_ids=None, sp_vals=None):
+    """An AnnIndexDesc over host arrays, and the arrays it points into."""
     keep = dict(levels=_np(graph.levels, np.uint8), adj0=_np(graph.adj0, np.int32),
                 upper_off=_np(graph.upper_off, np.int32), upper_adj=_np(graph.upper_adj, np.int32),
                 x_f32=_np(x_f32, np.float32), x_f16=_np(x_f16, np.uint16),
@@ -243,9 +245,39 @@ def ann_index_create(graph, metric, d, x_f32=None, x_f16=None, x_bf16=None, x_fp
     if keep["pq_codes"] is not None:
         D.pq_m = int(keep["pq_codes"].shape[1])
         D.pq_ksub = int(keep["pq_codebook"].shape[1])
+    return D, keep
+
+
+def ann_index_create(graph, metric, d, device=0, **arrays):
+    """Copy host arrays to the device.  `graph` has the attributes n, M, M0,
+    max_level, entry, levels, adj0, upper_off, upper_adj (exchange layout);
+    `arrays` are x_f32, x_f16, x_bf16, x_fp8, fp8_scale, pq_codebook,
+    pq_codes, sp_indptr, sp_ids, sp_vals (the ann_index_desc fields)."""
+    D, keep = _desc(graph, metric, d, **arrays)
     h = P()
     _check(lib().ann_index_create(C.byref(D), int(device), C.byref(h)))
     return Index(h, int(d), metric)
+
+
+def ann_index_save(path, graph, metric, d, **arrays):
+    """Write the host arrays of an index to an index file (host only)."""
+    D, keep = _desc(graph, metric, d, **arrays)
+    _check(lib().ann_index_save(C.byref(D), os.fsencode(path)))
+
+
+def ann_index_file_info(path):
+    """Check an index file on the host (no GPU) and describe it."""
+    out = AnnIndexInfo()
+    _check(lib().ann_index_file_info(os.fsencode(path), C.byref(out)))
+    return {f: getattr(out, f) for f, _ in AnnIndexInfo._fields_}
+
+
+def ann_index_load(path, device=0):
+    """Check an index file and copy its arrays to GPU `device`."""
+    info = ann_index_file_info(path)
+    h = P()
+    _check(lib().ann_index_load(os.fsencode(path), int(device), C.byref(h)))
+    return Index(h, int(info["d"]), "ip" if info["metric"] == METRIC["ip"] else "l2")
 
 
 def ann_index_free(index):

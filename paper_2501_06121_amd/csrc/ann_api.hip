@@ -154,6 +154,33 @@ int validate_graph(const ann_index_desc* D) {
 
 namespace ann {
 
+// Every host-side check of ann_index_create (no device involved).
+int check_desc(const ann_index_desc* D) {
+  if (D->n < 1 || D->n > INT32_MAX - 1) return fail(ANN_EINVAL, "n %lld outside [1, 2^31 - 2]", (long long)D->n);
+  if (D->d < 1) return fail(ANN_EINVAL, "d < 1");
+  if (D->metric != ANN_METRIC_L2 && D->metric != ANN_METRIC_IP) return fail(ANN_EINVAL, "unknown metric");
+  const bool dense = D->x_f32 || D->x_f16 || D->x_bf16 || D->x_fp8 || D->pq_codes;
+  if (dense && (D->d % 16 != 0 || D->d > 4096))
+    return fail(ANN_EFORMAT, "dense rows need d %% 16 == 0 and d <= 4096 (d=%d)", D->d);
+  if (D->x_fp8 && !D->fp8_scale) return fail(ANN_EINVAL, "x_fp8 without fp8_scale");
+  if (D->pq_codes || D->pq_codebook) {
+    if (!D->pq_codes || !D->pq_codebook || D->pq_ksub != 256 || D->pq_m < 1 || D->pq_m > 64 ||
+        D->d % D->pq_m != 0)
+      return fail(ANN_EFORMAT, "PQ needs codes, codebook, 256 centroids, 1 <= m <= 64, m | d");
+  }
+  if (D->sp_indptr) {
+    if (!D->sp_ids || !D->sp_vals) return fail(ANN_EINVAL, "sparse arrays incomplete");
+    if (D->metric != ANN_METRIC_IP) return fail(ANN_EFORMAT, "sparse rows support inner product only");
+    if (D->sp_indptr[0] != 0) return fail(ANN_EFORMAT, "sp_indptr[0] != 0");
+    for (int64_t v = 0; v < D->n; ++v)
+      if (D->sp_indptr[v + 1] < D->sp_indptr[v]) return fail(ANN_EFORMAT, "sp_indptr not monotone");
+    const int64_t nnz = D->sp_indptr[D->n];
+    for (int64_t j = 0; j < nnz; ++j)
+      if (D->sp_ids[j] >= D->d) return fail(ANN_EFORMAT, "sparse id %d >= vocabulary %d", D->sp_ids[j], D->d);
+  }
+  return validate_graph(D);
+}
+
 int default_waves(const ann_index* ix, const SearchParams& P);
 
 int ensure_workspace(ann_index* ix, Workspace& ws, int64_t slots, int64_t beam_cap) {
@@ -377,29 +404,7 @@ int ann_device_count(void) {
 int ann_index_create(const ann_index_desc* D, int device, ann_index** out) {
   if (!D || !out) return fail(ANN_EINVAL, "NULL argument");
   *out = nullptr;
-  if (D->n < 1 || D->n > INT32_MAX - 1) return fail(ANN_EINVAL, "n %lld outside [1, 2^31 - 2]", (long long)D->n);
-  if (D->d < 1) return fail(ANN_EINVAL, "d < 1");
-  if (D->metric != ANN_METRIC_L2 && D->metric != ANN_METRIC_IP) return fail(ANN_EINVAL, "unknown metric");
-  const bool dense = D->x_f32 || D->x_f16 || D->x_bf16 || D->x_fp8 || D->pq_codes;
-  if (dense && (D->d % 16 != 0 || D->d > 4096))
-    return fail(ANN_EFORMAT, "dense rows need d %% 16 == 0 and d <= 4096 (d=%d)", D->d);
-  if (D->x_fp8 && !D->fp8_scale) return fail(ANN_EINVAL, "x_fp8 without fp8_scale");
-  if (D->pq_codes || D->pq_codebook) {
-    if (!D->pq_codes || !D->pq_codebook || D->pq_ksub != 256 || D->pq_m < 1 || D->pq_m > 64 ||
-        D->d % D->pq_m != 0)
-      return fail(ANN_EFORMAT, "PQ needs codes, codebook, 256 centroids, 1 <= m <= 64, m | d");
-  }
-  if (D->sp_indptr) {
-    if (!D->sp_ids || !D->sp_vals) return fail(ANN_EINVAL, "sparse arrays incomplete");
-    if (D->metric != ANN_METRIC_IP) return fail(ANN_EFORMAT, "sparse rows support inner product only");
-    if (D->sp_indptr[0] != 0) return fail(ANN_EFORMAT, "sp_indptr[0] != 0");
-    for (int64_t v = 0; v < D->n; ++v)
-      if (D->sp_indptr[v + 1] < D->sp_indptr[v]) return fail(ANN_EFORMAT, "sp_indptr not monotone");
-    const int64_t nnz = D->sp_indptr[D->n];
-    for (int64_t j = 0; j < nnz; ++j)
-      if (D->sp_ids[j] >= D->d) return fail(ANN_EFORMAT, "sparse id %d >= vocabulary %d", D->sp_ids[j], D->d);
-  }
-  int rc = validate_graph(D);
+  int rc = check_desc(D);
   if (rc) return rc;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(ANN_ENODEV, "no GPU visible");
@@ -484,7 +489,9 @@ int ann_index_free(ann_index* ix) {
   return ANN_OK;
 }
 
-int ann_index_info_get(const ann_index* ix, ann_index_info* out) {
+int ann_index_info_get(const ann_index* ix, ann_info* out) { return ann_index_info(ix, out); }
+
+int ann_index_info(const ann_index* ix, ann_info* out) {
   if (!ix || !out) return fail(ANN_EINVAL, "NULL argument");
   out->n = ix->n; out->d = ix->d; out->metric = ix->metric; out->M = ix->M; out->M0 = ix->M0;
   out->max_level = ix->max_level; out->entry_point = ix->entry;

@@ -82,6 +82,9 @@ struct ann_index {
 
 namespace ann {
 
+// Every host-side check ann_index_create makes on a description (array
+// sizes, graph validity); no device is touched.
+int check_desc(const ann_index_desc* D);
 // Kernel parameters for a batch; every argument is checked on the host.
 int make_params(const ann_index* ix, const ann_batch* b, SearchParams* P);
 // Allocates (or grows) a workspace for `slots` slots, with room for beam

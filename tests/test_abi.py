@@ -31,7 +31,7 @@ def test_struct_layouts_match_the_c_header(tmp_path):
     """ctypes mirrors vs. what gcc lays out from include/ann.h."""
     import subprocess
     structs = {"ann_index_desc": ann.AnnIndexDesc, "ann_batch": ann.AnnBatch,
-               "ann_launch_cfg": ann.AnnLaunchCfg, "ann_index_info": ann.AnnIndexInfo,
+               "ann_launch_cfg": ann.AnnLaunchCfg, "ann_info": ann.AnnIndexInfo,
                "ann_server_cfg": ann.AnnServerCfg, "ann_request": ann.AnnRequest,
                "ann_completion": ann.AnnCompletion, "ann_ivf_batch": ann.AnnIvfBatch}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ann.h"', 'int main(void) {']
