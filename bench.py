@@ -227,8 +227,7 @@ def ivf_row(ann, torch, ivf, mode, Qd, k, nprobe, rerank, stream, gt, d, nlist, 
             "frac_of_fp32_vector_peak": round(tflops / FP32_VECTOR_PEAK, 4)}
 
 
-def serve_latency(ann, ix, Q, k, ef, mode, rerank, qps_peak, seconds=3.0, seed=0, streams=2,
-                  max_batch=2048, waves=4):
+def serve_latency(ann, ix, Q, k, ef, mode, rerank, qps_peak, seconds=3.0, seed=0, waves=4):
     """Open-loop Poisson arrivals at half the measured peak; p50/p99 ms.  At half
     load fewer queries are in flight, so the server gives each query `waves`
     wavefronts (4: lower latency than the throughput-optimal 2 at this load,
@@ -239,8 +238,7 @@ def serve_latency(ann, ix, Q, k, ef, mode, rerank, qps_peak, seconds=3.0, seed=0
     n_req = int(min(Q.shape[0] * 4, max(200, rate * seconds)))
     t_arr, qidx, _, _ = synth.arrivals(seed, n_req, rate, k_choices=(k,), ef_choices=(ef,),
                                        n_pool=Q.shape[0])
-    srv = ann.Server(ix, mode=mode, rerank=rerank, max_inflight=8192, max_batch=max_batch,
-                     streams=streams, k_max=max(k, 10), ef_max=ef)
+    srv = ann.Server(ix, mode=mode, rerank=rerank, max_inflight=8192, k_max=max(k, 10), ef_max=ef)
     lat = []
     try:
         t0 = time.perf_counter()
@@ -298,8 +296,7 @@ def serve_mix(ann, torch, n=None, seconds=3.0, rates=(5000, 10000, 20000, 35000,
         n_req = int(rate * seconds)
         t_arr, qidx, ks, efs = synth.arrivals(i_rate, n_req, rate, k_choices=(10, 100),
                                               ef_choices=(64, 128, 256, 512), n_pool=Q.shape[0])
-        srv = ann.Server(ix, mode="f16", rerank=rerank, max_inflight=16384, max_batch=2048,
-                         streams=2, k_max=100, ef_max=512)
+        srv = ann.Server(ix, mode="f16", rerank=rerank, max_inflight=16384, k_max=100, ef_max=512)
         lat = np.zeros(n_req)
         got = {}
         try:

@@ -608,18 +608,54 @@ int ann_ivf_search(ann_ivf* v, const ann_ivf_batch* b, void* stream);
 
 /* ---- serving: continuous batching ------------------------------------------ */
 
+/*
+ * A server keeps the index resident and answers single requests (one query
+ * each, with its own k and ef) submitted from any host thread, with the
+ * search above (the paper answers one query at a time, Section 3; here the
+ * requests in flight share the GPU).
+ *
+ * Admission is per slot.  One persistent search kernel runs `slots`
+ * workgroups ("slots", each serving one request at a time).  Submitted
+ * requests wait in a host queue (at most queue_cap) until a ring entry in
+ * pinned host memory is free (at most max_inflight requests on the device,
+ * running or waiting for a slot); the server's host thread writes them into
+ * the ring and publishes them in submission order.  The first slot that is
+ * free claims the next published request, so a request that arrives while
+ * others run starts as soon as any slot is free, and its work overlaps
+ * theirs on the device.  The kernel writes each result into its ring entry
+ * with a completion flag, and the host thread moves it to the completion
+ * list.  When nothing has been published for idle_us the kernel ends, and
+ * the next request launches it again.
+ *
+ * Results equal ann_search_ex's for the same query, k, ef, mode and rerank,
+ * bit for bit, whatever else is in flight.
+ *
+ * ann_server_cfg:
+ *   mode, rerank   as in ann_batch (dense modes); the launch shape (waves
+ *                  per query, lanes per row, beam layout) is the index's for
+ *                  `mode` (ann_set_launch) when the server is created
+ *   max_inflight   ring entries, >= 1 (host memory: 4 d + 12 k_max + 40 bytes each)
+ *   slots          workgroups of the kernel; 0: what the compute units hold
+ *                  at once (occupancy), halved until the visited bitsets and
+ *                  beam lists fit hbm_budget
+ *   k_max, ef_max  bounds of the requests' k and ef
+ *   queue_cap      waiting requests before ann_server_submit returns ANN_EAGAIN
+ *   idle_us        the kernel ends after this long without a new request;
+ *                  0: 2,000
+ *   hbm_budget     bytes of device memory the slots' workspace may use
+ */
 typedef struct ann_server ann_server;
 
 typedef struct ann_server_cfg {
-  int32_t mode;          /* enum ann_mode (dense modes) */
-  int32_t rerank;        /* as in ann_batch */
-  int32_t max_inflight;  /* queries on the device at once (slots), > 0 */
-  int32_t max_batch;     /* largest batch one launch takes, > 0 */
-  int32_t streams;       /* concurrent launches (1..4) */
-  int32_t k_max;         /* upper bound of request k, <= ANN_K_MAX */
-  int32_t ef_max;        /* upper bound of request ef, <= ANN_EF_MAX */
-  int32_t queue_cap;     /* waiting requests before ANN_EAGAIN */
-  int64_t hbm_budget;    /* bytes of device memory the server may use */
+  int32_t mode;
+  int32_t rerank;
+  int32_t max_inflight;
+  int32_t slots;
+  int32_t k_max;
+  int32_t ef_max;
+  int32_t queue_cap;
+  int32_t idle_us;
+  int64_t hbm_budget;
 } ann_server_cfg;
 
 typedef struct ann_request {
@@ -628,24 +664,45 @@ typedef struct ann_request {
   int32_t k, ef;
 } ann_request;
 
+/* A finished request.  t_*: host steady clock in seconds (submitted, written
+ * into the ring, seen done); d_*: the device clock in seconds (claimed by a
+ * slot, finished), comparable between the requests of one server; slot: the
+ * workgroup that served it. */
 typedef struct ann_completion {
   uint64_t tag;
-  int32_t status;        /* ANN_OK or an error code */
+  int32_t status;        /* ANN_OK, or ANN_EBUDGET if k or ef had to be clamped */
   int32_t k;
   int64_t ids[ANN_K_MAX];
   float dists[ANN_K_MAX];
-  double t_submit, t_start, t_done;  /* seconds, steady clock */
+  double t_submit, t_start, t_done;
+  double d_start, d_done;
+  int32_t slot;
+  int32_t reserved;
 } ann_completion;
 
-/* Starts a server thread that admits queued requests into free slots while
- * earlier batches still run, launching each admitted batch on its own stream. */
+/* What a server runs with. */
+typedef struct ann_server_state {
+  int32_t slots;
+  int32_t ring;
+  int32_t waves_per_query;
+  int32_t lanes_per_row;
+  int64_t queued;        /* requests waiting for a ring entry */
+} ann_server_state;
+
+/* Validates cfg, allocates the slots' workspace (device) and the ring
+ * (pinned host memory), starts the host thread.  ANN_EBUDGET if one slot does
+ * not fit hbm_budget or ef_max does not fit on chip. */
 int ann_server_create(const ann_index* ix, const ann_server_cfg* cfg, ann_server** out);
-/* Copies the request into the queue; ANN_EAGAIN if the queue is full. */
+/* Copies the request into the queue; ANN_EAGAIN if the queue is full,
+ * ANN_EINVAL for k or ef outside the bounds. */
 int ann_server_submit(ann_server* s, const ann_request* r);
 /* Moves up to `max` finished requests into out[]; returns how many (>= 0),
  * or a negative error code.  Non-blocking. */
 int ann_server_poll(ann_server* s, ann_completion* out, int32_t max);
-/* Stops admitting, drains in-flight work, joins the thread, frees memory. */
+int ann_server_info(const ann_server* s, ann_server_state* out);
+/* Stops admitting: requests not yet claimed by a slot are dropped, running
+ * ones finish; then frees the server.  Returns the first error of the
+ * server's host thread, if any. */
 int ann_server_destroy(ann_server* s);
 
 /* ---- misc -------------------------------------------------------------- */

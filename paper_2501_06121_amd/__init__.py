@@ -62,9 +62,14 @@ class AnnLaunchCfg(C.Structure):
 
 
 class AnnServerCfg(C.Structure):
-    _fields_ = [("mode", I32), ("rerank", I32), ("max_inflight", I32), ("max_batch", I32),
-                ("streams", I32), ("k_max", I32), ("ef_max", I32), ("queue_cap", I32),
+    _fields_ = [("mode", I32), ("rerank", I32), ("max_inflight", I32), ("slots", I32),
+                ("k_max", I32), ("ef_max", I32), ("queue_cap", I32), ("idle_us", I32),
                 ("hbm_budget", I64)]
+
+
+class AnnServerState(C.Structure):
+    _fields_ = [("slots", I32), ("ring", I32), ("waves_per_query", I32), ("lanes_per_row", I32),
+                ("queued", I64)]
 
 
 class AnnRequest(C.Structure):
@@ -74,7 +79,8 @@ class AnnRequest(C.Structure):
 class AnnCompletion(C.Structure):
     _fields_ = [("tag", U64), ("status", I32), ("k", I32), ("ids", I64 * ANN_K_MAX),
                 ("dists", C.c_float * ANN_K_MAX), ("t_submit", F64), ("t_start", F64),
-                ("t_done", F64)]
+                ("t_done", F64), ("d_start", F64), ("d_done", F64), ("slot", I32),
+                ("reserved", I32)]
 
 
 # Every exported symbol and its argument types; the CPU tests check that the
@@ -120,6 +126,7 @@ SIGNATURES = {
     "ann_server_create": ([P, P, P], C.c_int),
     "ann_server_submit": ([P, P], C.c_int),
     "ann_server_poll": ([P, P, I32], C.c_int),
+    "ann_server_info": ([P, P], C.c_int),
     "ann_server_destroy": ([P], C.c_int),
     "ann_last_error": ([], C.c_char_p),
     "ann_version": ([], C.c_int),
@@ -652,12 +659,13 @@ def ann_ivf_search(ivf, queries, k, nprobe, mode="f32", rerank=0, want_probes=Fa
 
 
 class Server:
-    """Continuous-batching server around ann_server_* (host query vectors)."""
+    """Continuous batching with per-slot admission around ann_server_* (host
+    query vectors in, completions out)."""
 
-    def __init__(self, index, mode="f16", rerank=0, max_inflight=4096, max_batch=1024,
-                 streams=2, k_max=100, ef_max=512, queue_cap=1 << 16, hbm_budget=8 << 30):
-        cfg = AnnServerCfg(MODE[mode], int(rerank), int(max_inflight), int(max_batch),
-                           int(streams), int(k_max), int(ef_max), int(queue_cap), int(hbm_budget))
+    def __init__(self, index, mode="f16", rerank=0, max_inflight=4096, slots=0, k_max=100,
+                 ef_max=512, queue_cap=1 << 16, idle_us=0, hbm_budget=8 << 30):
+        cfg = AnnServerCfg(MODE[mode], int(rerank), int(max_inflight), int(slots), int(k_max),
+                           int(ef_max), int(queue_cap), int(idle_us), int(hbm_budget))
         self.index = index
         self.handle = P()
         _check(lib().ann_server_create(index.handle, C.byref(cfg), C.byref(self.handle)))
@@ -682,8 +690,14 @@ class Server:
             kk = c.k
             out.append(dict(tag=c.tag, status=c.status, ids=np.array(c.ids[:kk], np.int64),
                             dists=np.array(c.dists[:kk], np.float32), t_submit=c.t_submit,
-                            t_start=c.t_start, t_done=c.t_done))
+                            t_start=c.t_start, t_done=c.t_done, d_start=c.d_start,
+                            d_done=c.d_done, slot=c.slot))
         return out
+
+    def info(self):
+        st = AnnServerState()
+        _check(lib().ann_server_info(self.handle, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in AnnServerState._fields_}
 
     def close(self):
         if self.handle:

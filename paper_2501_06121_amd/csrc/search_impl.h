@@ -142,7 +142,8 @@ struct Lds {
 // expansion (no barrier follows an expansion without new entries) never sees
 // it overwritten by the next one.
 enum { CTL_QUERY = 0, CTL_M = 1, CTL_W = 2, CTL_HINT = 3, CTL_VISITED = 4, CTL_VLOG = 5,
-       CTL_VLOG_OVF = 6, CTL_FLUSH = 7, CTL_R0 = 8, CTL_M_ODD = 9 };
+       CTL_VLOG_OVF = 6, CTL_FLUSH = 7, CTL_R0 = 8, CTL_M_ODD = 9, CTL_SEQ_LO = 10,
+       CTL_SEQ_HI = 11 };
 
 __device__ Lds carve(char* base, const SearchParams& p) {
   Lds s;
@@ -1258,6 +1259,47 @@ __device__ __forceinline__ void run_query(const SearchParams& p, const Lds& s, P
 #define ANN_OCCUPANCY
 #endif
 
+// Claims the next published request of a server's ring (thread 0 of a
+// workgroup): its sequence number, or -1 when the host asks the kernel to end
+// or when nothing has been published for idle_ticks.  Every path of the wait
+// ends: the idle clock runs unless new requests keep arriving.
+__device__ int64_t ring_claim(const RingArgs& r) {
+  uint64_t seen = ~0ull;
+  uint64_t t_idle = (uint64_t)wall_clock64();
+  int64_t spins = 0;
+  while (true) {
+    if (__hip_atomic_load(r.dev_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return -1;
+    const uint64_t now = (uint64_t)wall_clock64();
+    uint64_t lp = __hip_atomic_load(r.last_poll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (now - lp >= r.poll_ticks &&
+        __hip_atomic_compare_exchange_strong(r.last_poll, &lp, now, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+      // this workgroup is the poller until poll_ticks have passed
+      const uint64_t ht = __hip_atomic_load(r.host_tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_fetch_max(r.mirror, ht, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (__hip_atomic_load(r.host_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))
+        __hip_atomic_store(r.dev_stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const uint64_t tail = __hip_atomic_load(r.mirror, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    if (tail != seen) { seen = tail; t_idle = now; spins = 0; }
+    uint64_t h = __hip_atomic_load(r.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (h < tail) {
+      if (__hip_atomic_compare_exchange_strong(r.head, &h, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT)) {
+        // the host wrote the entry before publishing it: read it fresh
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+        return (int64_t)h;
+      }
+      continue;
+    }
+    if (now - t_idle > r.idle_ticks || ++spins > r.idle_spins) return -1;
+    // about 7 us between looks: the waiting slots' reads of the control
+    // words stay a small load on the L2
+    __builtin_amdgcn_s_sleep(127);
+    __builtin_amdgcn_s_sleep(127);
+  }
+}
+
 template <class Policy, bool GLIST>
 __global__ void __launch_bounds__(512) ANN_OCCUPANCY search_kernel(SearchParams p) {
   extern __shared__ __align__(16) char lds_raw[];
@@ -1269,6 +1311,37 @@ __global__ void __launch_bounds__(512) ANN_OCCUPANCY search_kernel(SearchParams 
   if (p.nq_dev) {
     const int64_t nd = (int64_t)uniform_int(*p.nq_dev);
     nq = nd < 0 ? 0 : nd < p.nq ? nd : p.nq;
+  }
+  if (p.ring.cap > 0) {
+    // server: one request of the ring at a time
+    const RingArgs& r = p.ring;
+    while (true) {
+      if (threadIdx.x == 0) {
+        const int64_t seq = ring_claim(r);
+        s.ctl[CTL_QUERY] = seq < 0 ? -1 : (int)(seq % r.cap);
+        s.ctl[CTL_SEQ_LO] = (int)(uint32_t)(uint64_t)seq;
+        s.ctl[CTL_SEQ_HI] = (int)(uint32_t)((uint64_t)seq >> 32);
+        if (seq >= 0) r.t_start[seq % r.cap] = (uint64_t)wall_clock64();
+      }
+      __syncthreads();
+      const int pos = uniform_int(s.ctl[CTL_QUERY]);
+      const uint64_t seq = ((uint64_t)(uint32_t)s.ctl[CTL_SEQ_HI] << 32) | (uint32_t)s.ctl[CTL_SEQ_LO];
+      __syncthreads();
+      if (pos < 0) break;
+      // every wave reads the entry the host wrote before publishing it
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+      run_query<Policy, GLIST>(p, s, pol, slot, (int64_t)pos);
+      // the results (in host memory) are visible before the completion flag
+      __threadfence_system();
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        r.t_done[pos] = (uint64_t)wall_clock64();
+        r.served_by[pos] = slot;
+        __threadfence_system();
+        __hip_atomic_store(&r.done[pos], seq + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+    }
+    return;
   }
   while (true) {
     if (threadIdx.x == 0) s.ctl[CTL_QUERY] = atomicAdd(p.counter, 1);

@@ -9,6 +9,33 @@ namespace ann {
 enum { MODE_F32 = 0, MODE_F16 = 1, MODE_BF16 = 2, MODE_FP8 = 3, MODE_PQ = 4, MODE_SPARSE = 5 };
 enum { METRIC_L2 = 0, METRIC_IP = 1 };
 
+// Request ring of a server (ring.cap > 0): the persistent kernel's
+// workgroups claim requests one at a time, in publication order, from a ring
+// in host memory instead of taking queries from a batch.  The host writes an
+// entry (query, k, ef), then publishes it by raising *host_tail; one waiting
+// workgroup at a time copies *host_tail into *mirror every poll_ticks, the
+// others read the mirror (device memory), and a workgroup claims request
+// `seq` by advancing *head from seq to seq + 1.  When a request is done its
+// results are in host memory and done[seq % cap] = seq + 1.  A workgroup
+// stops waiting when *host_stop is set (seen through *dev_stop) or when no
+// request has been published for idle_ticks; the kernel then ends, and the
+// host launches it again for the next request.
+struct RingArgs {
+  int64_t cap;                      // entries; 0: no ring (batch mode)
+  const uint64_t* host_tail;        // host memory: requests published
+  const uint32_t* host_stop;        // host memory: nonzero asks the kernel to end
+  uint64_t* head;                   // device: requests claimed
+  uint64_t* mirror;                 // device: the last host_tail read
+  uint64_t* last_poll;              // device: clock of the last read of host_tail
+  uint32_t* dev_stop;               // device: host_stop as seen by a poller
+  uint64_t* done;                   // host memory [cap]: seq + 1 once request seq is done
+  uint64_t* t_start;                // host memory [cap]: device clock at claim
+  uint64_t* t_done;                 // host memory [cap]: device clock at completion
+  int32_t* served_by;               // host memory [cap]: the workgroup that served it
+  uint64_t idle_ticks, poll_ticks;  // device clock ticks
+  int64_t idle_spins;               // the same bound counted in waits (about 7 us each)
+};
+
 struct SearchParams {
   int mode, metric;
   int d, nchunks, lanes_per_row;
@@ -58,6 +85,7 @@ struct SearchParams {
   int32_t* vlog;
   int vlog_cap;
   int32_t* counter;
+  RingArgs ring;
 };
 
 // Entries of the sparse query's hash table in LDS (at most half filled).

@@ -1,21 +1,19 @@
-// Continuous-batching server over the persistent search kernel.
+// Continuous batching over the persistent search kernel, admitted per slot.
 //
-// One host thread admits queued requests into free launch lanes.  Each lane
-// owns a HIP stream, a workspace (visited bitsets for its slots), pinned
-// staging buffers and device buffers for one batch; a lane is free again
-// once its completion event has fired.  Requests that arrive while other
-// batches run are admitted into the next free lane, so batches of different
-// sizes and different (k, ef) overlap on the device.  Admission is bounded by
-// max_inflight (queries on the device), max_batch (queries per launch) and
-// the device memory budget fixed at creation.
+// The server keeps one persistent search kernel on the device whose
+// workgroups ("slots") take requests one at a time from a ring in pinned
+// host memory (RingArgs in search_kernels.h).  A host thread moves submitted
+// requests into free ring entries and publishes them; the first slot that
+// is free claims the next published request, so a request that arrives while
+// others run starts as soon as any one slot is free, without waiting for a
+// batch to end, and its work overlaps theirs on the device.  Results are
+// written by the kernel straight into the ring entry (host memory) with a
+// completion flag; the host thread collects them.
 //
-// Each lane replays one captured HIP graph (queue-counter reset + persistent
-// search kernel) per batch; the kernel reads the batch size from device
-// memory, so the same graph serves batches of every size.
-//
-// Results do not depend on how requests were batched: the kernel evaluates
-// every query with the same fixed arithmetic whatever its neighbours in the
-// batch.
+// The kernel ends by itself when nothing has been published for idle_us
+// (or when the server stops); the host thread launches it again when new
+// requests are waiting.  Results do not depend on which slot serves a
+// request or on what else runs: every key is evaluated in the fixed order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -40,44 +38,21 @@ double now_s() {
 }
 
 struct Req {
-  uint64_t tag;
-  int32_t k, ef;
-  double t_submit;
+  uint64_t tag = 0;
+  int32_t k = 0, ef = 0;
+  double t_submit = 0.0, t_start = 0.0;
   std::vector<float> q;
 };
 
 struct Done {
   uint64_t tag;
-  int32_t status, k;
+  int32_t status, k, slot;
   std::vector<int64_t> ids;
   std::vector<float> dists;
-  double t_submit, t_start, t_done;
+  double t_submit, t_start, t_done, d_start, d_done;
 };
 
-struct Lane {
-  hipStream_t st = nullptr;
-  hipEvent_t ev = nullptr;
-  Workspace ws;
-  float* dq = nullptr;
-  int32_t* dk = nullptr;
-  int32_t* def = nullptr;
-  int64_t* dids = nullptr;
-  float* dd = nullptr;
-  int32_t* dstat = nullptr;
-  int32_t* dnq = nullptr;            // query count of the batch on the device
-  int32_t* hnq = nullptr;
-  hipGraph_t graph = nullptr;        // [counter reset, search] captured once
-  hipGraphExec_t exec = nullptr;
-  float* hq = nullptr;
-  int32_t* hk = nullptr;
-  int32_t* hef = nullptr;
-  int64_t* hids = nullptr;
-  float* hd = nullptr;
-  int32_t* hstat = nullptr;
-  std::vector<Req> batch;
-  bool busy = false;
-  double t_start = 0.0;
-};
+constexpr double kPollUs = 2.0;     // how often one waiting slot reads the host's ring tail
 
 }  // namespace
 
@@ -85,166 +60,182 @@ struct ann_server {
   ann_index* ix = nullptr;
   ann_server_cfg cfg{};
   int64_t slots = 0;
-  std::vector<Lane> lanes;
-  SearchParams proto{};              // kernel parameters shared by the lanes
+  int64_t R = 0;                     // ring entries
+  SearchParams P{};
+  Workspace ws;
+  hipStream_t st = nullptr;
+  hipEvent_t ev = nullptr;
+  bool running = false;
+  double clock_hz = 1e8;
+  // ring in pinned host memory (h_*: host addresses, d_*: the same memory as
+  // the device addresses it)
+  void* hblock = nullptr;
+  uint64_t* h_tail = nullptr;
+  uint32_t* h_stop = nullptr;
+  float* h_q = nullptr;
+  int32_t* h_k = nullptr;
+  int32_t* h_ef = nullptr;
+  int64_t* h_ids = nullptr;
+  float* h_d = nullptr;
+  int32_t* h_status = nullptr;
+  uint64_t* h_done = nullptr;
+  uint64_t* h_tstart = nullptr;
+  uint64_t* h_tdone = nullptr;
+  int32_t* h_served = nullptr;
+  uint64_t* d_ctl = nullptr;         // device: head, mirror, last poll, stop
+  std::vector<int64_t> entry_seq;    // request occupying each entry, -1 when free
+  std::vector<Req> entry_req;
+  uint64_t next_seq = 0;             // requests published
+  uint64_t oldest = 0;               // every request below this one has been collected
+  uint64_t completed = 0;
   std::mutex mu;
   std::condition_variable cv;
   std::deque<Req> queue;
   std::deque<Done> done;
-  int64_t inflight = 0;
   bool stop = false;
   int loop_error = ANN_OK;
   std::thread th;
 
-  int launch(Lane& L, std::vector<Req>&& reqs);
-  int capture(Lane& L);
-  void collect(Lane& L);
+  int launch();
+  bool collect();
+  bool admit();
   void loop();
-  void free_lanes();
+  void release();
 };
 
-int ann_server::launch(Lane& L, std::vector<Req>&& reqs) {
-  const int m = (int)reqs.size();
-  const int d = ix->d;
-  for (int i = 0; i < m; ++i) {
-    std::memcpy(L.hq + (size_t)i * d, reqs[i].q.data(), sizeof(float) * d);
-    L.hk[i] = reqs[i].k;
-    L.hef[i] = reqs[i].ef;
-  }
-  HIP_OR_RETURN(hipMemcpyAsync(L.dq, L.hq, sizeof(float) * (size_t)m * d, hipMemcpyHostToDevice, L.st), "H2D queries");
-  HIP_OR_RETURN(hipMemcpyAsync(L.dk, L.hk, sizeof(int32_t) * m, hipMemcpyHostToDevice, L.st), "H2D k");
-  HIP_OR_RETURN(hipMemcpyAsync(L.def, L.hef, sizeof(int32_t) * m, hipMemcpyHostToDevice, L.st), "H2D ef");
-  *L.hnq = m;
-  HIP_OR_RETURN(hipMemcpyAsync(L.dnq, L.hnq, sizeof(int32_t), hipMemcpyHostToDevice, L.st), "H2D nq");
-  HIP_OR_RETURN(hipGraphLaunch(L.exec, L.st), "hipGraphLaunch");
-  const size_t kk = (size_t)m * cfg.k_max;
-  HIP_OR_RETURN(hipMemcpyAsync(L.hids, L.dids, sizeof(int64_t) * kk, hipMemcpyDeviceToHost, L.st), "D2H ids");
-  HIP_OR_RETURN(hipMemcpyAsync(L.hd, L.dd, sizeof(float) * kk, hipMemcpyDeviceToHost, L.st), "D2H dists");
-  HIP_OR_RETURN(hipMemcpyAsync(L.hstat, L.dstat, sizeof(int32_t) * m, hipMemcpyDeviceToHost, L.st), "D2H status");
-  HIP_OR_RETURN(hipEventRecord(L.ev, L.st), "hipEventRecord");
-  L.batch = std::move(reqs);
-  L.busy = true;
-  L.t_start = now_s();
-  return ANN_OK;
-}
-
-// Records the lane's two kernels (queue-counter reset and the persistent
-// search) as a graph: the batch size is read from L.dnq on the device, so one
-// graph serves every batch of the lane.
-int ann_server::capture(Lane& L) {
-  SearchParams P = proto;
-  P.nq = cfg.max_batch;
-  P.nq_dev = L.dnq;
-  P.queries = L.dq;
-  P.k_arr = L.dk;
-  P.ef_arr = L.def;
-  P.out_ids = L.dids;
-  P.out_dists = L.dd;
-  P.out_status = L.dstat;
-  bind_workspace(P, L.ws);
+int ann_server::launch() {
   const size_t lds = lds_bytes(P);
-  if (lds > 65536) {
-    const void* fn = kernel_symbol(P);
-    if (fn) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  }
-  HIP_OR_RETURN(hipStreamBeginCapture(L.st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-  const hipError_t le = launch_search(P, (int)std::min<int64_t>(slots, cfg.max_batch), lds, L.st);
-  hipGraph_t g = nullptr;
-  const hipError_t ce = hipStreamEndCapture(L.st, &g);
-  if (le != hipSuccess) { if (g) (void)hipGraphDestroy(g); return hip_fail(le, "captured search launch"); }
-  HIP_OR_RETURN(ce, "hipStreamEndCapture");
-  L.graph = g;
-  HIP_OR_RETURN(hipGraphInstantiate(&L.exec, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+  const void* fn = kernel_symbol(P);
+  if (!fn) return fail(ANN_EUNSUP, "no search kernel for the server's mode");
+  if (lds > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  SearchParams arg = P;
+  void* args[] = {&arg};
+  HIP_OR_RETURN(hipLaunchKernel(fn, dim3((unsigned)slots), dim3(64 * P.waves_per_query), args, lds, st),
+                "server kernel launch");
+  HIP_OR_RETURN(hipEventRecord(ev, st), "hipEventRecord");
+  running = true;
   return ANN_OK;
 }
 
-void ann_server::collect(Lane& L) {
-  const double t = now_s();
+// Moves finished requests from the ring to the completion list.
+bool ann_server::collect() {
+  bool any = false;
   std::vector<Done> out;
-  out.reserve(L.batch.size());
-  for (size_t i = 0; i < L.batch.size(); ++i) {
-    const Req& r = L.batch[i];
+  const double t = now_s();
+  for (uint64_t seq = oldest; seq < next_seq; ++seq) {
+    const int64_t e = (int64_t)(seq % (uint64_t)R);
+    if (entry_seq[e] != (int64_t)seq) continue;
+    if (__atomic_load_n(&h_done[e], __ATOMIC_ACQUIRE) != seq + 1) continue;
+    Req& r = entry_req[e];
     Done c;
     c.tag = r.tag;
-    c.status = L.hstat[i] == 0 ? ANN_OK : ANN_EBUDGET;
+    c.status = h_status[e] == 0 ? ANN_OK : ANN_EBUDGET;
     c.k = r.k;
-    c.ids.assign(L.hids + i * cfg.k_max, L.hids + i * cfg.k_max + r.k);
-    c.dists.assign(L.hd + i * cfg.k_max, L.hd + i * cfg.k_max + r.k);
+    c.slot = h_served[e];
+    c.ids.assign(h_ids + e * cfg.k_max, h_ids + e * cfg.k_max + r.k);
+    c.dists.assign(h_d + e * cfg.k_max, h_d + e * cfg.k_max + r.k);
     c.t_submit = r.t_submit;
-    c.t_start = L.t_start;
+    c.t_start = r.t_start;
     c.t_done = t;
+    c.d_start = (double)h_tstart[e] / clock_hz;
+    c.d_done = (double)h_tdone[e] / clock_hz;
     out.push_back(std::move(c));
+    entry_seq[e] = -1;
+    ++completed;
+    any = true;
   }
-  std::lock_guard<std::mutex> lk(mu);
-  for (auto& c : out) done.push_back(std::move(c));
-  inflight -= (int64_t)L.batch.size();
-  L.batch.clear();
-  L.busy = false;
+  while (oldest < next_seq && entry_seq[oldest % (uint64_t)R] != (int64_t)oldest) ++oldest;
+  if (any) {
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto& c : out) done.push_back(std::move(c));
+  }
+  return any;
+}
+
+// Writes waiting requests into free ring entries and publishes them.
+bool ann_server::admit() {
+  std::vector<Req> take;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if (stop) return false;
+    uint64_t seq = next_seq;
+    while (!queue.empty() && seq - completed < (uint64_t)R &&
+           entry_seq[seq % (uint64_t)R] == -1) {
+      take.push_back(std::move(queue.front()));
+      queue.pop_front();
+      ++seq;
+    }
+  }
+  if (take.empty()) return false;
+  const int d = ix->d;
+  const double t = now_s();
+  for (Req& r : take) {
+    const int64_t e = (int64_t)(next_seq % (uint64_t)R);
+    std::memcpy(h_q + (size_t)e * d, r.q.data(), sizeof(float) * d);
+    h_k[e] = r.k;
+    h_ef[e] = r.ef;
+    h_done[e] = 0;
+    r.t_start = t;
+    entry_seq[e] = (int64_t)next_seq;
+    entry_req[e] = std::move(r);
+    ++next_seq;
+  }
+  // the entries are written before the tail that publishes them
+  __atomic_store_n(h_tail, next_seq, __ATOMIC_RELEASE);
+  return true;
 }
 
 void ann_server::loop() {
   if (hipSetDevice(ix->device) != hipSuccess) { loop_error = ANN_EHIP; return; }
   while (true) {
-    bool progressed = false;
-    for (Lane& L : lanes) {
-      if (!L.busy) continue;
-      const hipError_t q = hipEventQuery(L.ev);
-      if (q == hipSuccess) { collect(L); progressed = true; }
-      else if (q != hipErrorNotReady) { loop_error = hip_fail(q, "server batch"); collect(L); }
-    }
-    bool any_busy = false;
-    for (Lane& L : lanes) {
-      if (L.busy) { any_busy = true; continue; }
-      std::vector<Req> take;
-      {
-        std::lock_guard<std::mutex> lk(mu);
-        if (stop) break;
-        const int64_t room = std::min<int64_t>(cfg.max_inflight - inflight, cfg.max_batch);
-        const int64_t m = std::min<int64_t>(room, (int64_t)queue.size());
-        if (m <= 0) continue;
-        for (int64_t i = 0; i < m; ++i) { take.push_back(std::move(queue.front())); queue.pop_front(); }
-        inflight += m;
+    bool progressed = collect();
+    if (running) {
+      const hipError_t q = hipEventQuery(ev);
+      if (q == hipSuccess) {
+        running = false;
+      } else if (q != hipErrorNotReady) {
+        loop_error = hip_fail(q, "server kernel");
+        running = false;
       }
-      const int rc = launch(L, std::move(take));
-      if (rc) {
-        // launch() keeps `take` untouched on failure: report its requests
-        loop_error = rc;
-        const double t = now_s();
-        std::lock_guard<std::mutex> lk(mu);
-        for (const Req& r : take) done.push_back(Done{r.tag, rc, 0, {}, {}, r.t_submit, t, t});
-        inflight -= (int64_t)take.size();
-      }
-      progressed = true;
-      any_busy = any_busy || L.busy;
     }
+    progressed = admit() || progressed;
+    bool stopping;
     {
+      std::lock_guard<std::mutex> lk(mu);
+      stopping = stop;
+    }
+    if (stopping) {
+      // no new work: the running requests finish, waiting ones are dropped
+      __atomic_store_n(h_stop, 1u, __ATOMIC_RELEASE);
+      if (running) (void)hipEventSynchronize(ev);
+      running = false;
+      collect();
+      return;
+    }
+    // a published request that no running kernel will claim: (re)launch
+    if (!running && next_seq > completed && loop_error == ANN_OK) {
+      const int rc = launch();
+      if (rc) loop_error = rc;
+      progressed = true;
+    }
+    if (!progressed) {
       std::unique_lock<std::mutex> lk(mu);
-      if (stop && !any_busy) {
-        bool busy = false;
-        for (Lane& L : lanes) busy = busy || L.busy;
-        if (!busy) break;
-      }
-      if (!progressed) cv.wait_for(lk, std::chrono::microseconds(any_busy ? 20 : 500));
+      cv.wait_for(lk, std::chrono::microseconds(next_seq > completed ? 20 : 500));
     }
   }
 }
 
-void ann_server::free_lanes() {
-  for (Lane& L : lanes) {
-    if (L.st) (void)hipStreamSynchronize(L.st);
-    L.ws.release();
-    if (L.exec) (void)hipGraphExecDestroy(L.exec);
-    if (L.graph) (void)hipGraphDestroy(L.graph);
-    void* dev[] = {L.dq, L.dk, L.def, L.dids, L.dd, L.dstat, L.dnq};
-    for (void* p : dev)
-      if (p) (void)hipFree(p);
-    void* host[] = {L.hq, L.hk, L.hef, L.hids, L.hd, L.hstat, L.hnq};
-    for (void* p : host)
-      if (p) (void)hipHostFree(p);
-    if (L.ev) (void)hipEventDestroy(L.ev);
-    if (L.st) (void)hipStreamDestroy(L.st);
-  }
-  lanes.clear();
+void ann_server::release() {
+  if (st) (void)hipStreamSynchronize(st);
+  ws.release();
+  if (d_ctl) (void)hipFree(d_ctl);
+  if (hblock) (void)hipHostFree(hblock);
+  if (ev) (void)hipEventDestroy(ev);
+  if (st) (void)hipStreamDestroy(st);
+  d_ctl = nullptr;
+  hblock = nullptr;
+  ev = nullptr;
+  st = nullptr;
 }
 
 extern "C" {
@@ -253,14 +244,15 @@ int ann_server_create(const ann_index* cix, const ann_server_cfg* cfg, ann_serve
   if (!cix || !cfg || !out) return fail(ANN_EINVAL, "NULL argument");
   *out = nullptr;
   const ann_server_cfg& c = *cfg;
-  if (c.mode < ANN_MODE_F32 || c.mode > ANN_MODE_FP8) return fail(ANN_EINVAL, "server modes are the dense ones (0..3)");
-  if (c.rerank < 0 || c.max_inflight < 1 || c.max_batch < 1 || c.streams < 1 || c.streams > 4 ||
-      c.k_max < 1 || c.k_max > ANN_K_MAX || c.ef_max < 1 || c.queue_cap < 1 || c.hbm_budget < 1)
+  if (c.mode < ANN_MODE_F32 || c.mode > ANN_MODE_FP8)
+    return fail(ANN_EINVAL, "server modes are the dense ones (0..3)");
+  if (c.rerank < 0 || c.max_inflight < 1 || c.slots < 0 || c.k_max < 1 || c.k_max > ANN_K_MAX ||
+      c.ef_max < 1 || c.queue_cap < 1 || c.hbm_budget < 1 || c.idle_us < 0)
     return fail(ANN_EINVAL, "bad server configuration");
   if (std::max(c.ef_max, c.k_max) > ANN_EF_MAX) return fail(ANN_EBUDGET, "ef_max above ANN_EF_MAX");
   ann_index* ix = const_cast<ann_index*>(cix);
-  // a dry batch validates mode, rerank and the on-chip memory for ef_max,
-  // and gives the kernel parameters every lane shares
+  // a dry batch validates mode, rerank and the on-chip memory for ef_max and
+  // gives the kernel parameters
   ann_batch b;
   std::memset(&b, 0, sizeof b);
   b.mode = c.mode; b.rerank = c.rerank; b.nq = 0; b.k_all = 1; b.ef_all = 1;
@@ -268,49 +260,89 @@ int ann_server_create(const ann_index* cix, const ann_server_cfg* cfg, ann_serve
   SearchParams P;
   int rc = make_params(ix, &b, &P);
   if (rc) return rc;
-  const SearchParams proto = P;
   std::unique_ptr<ann_server> s(new ann_server);
   s->ix = ix;
   s->cfg = c;
-  const int64_t max_batch = std::min<int64_t>(c.max_batch, c.max_inflight);
-  // device memory of one lane: batch buffers + workspace
-  const int64_t batch_bytes = max_batch * ((int64_t)ix->d * 4 + 8 + (int64_t)c.k_max * 12 + 4);
-  P.nq = max_batch;
-  int64_t slots = pick_slots(ix, P, 0);
-  const int64_t per_slot = slot_bytes(ix->n) + (proto.glist ? (int64_t)proto.ef_cap * 16 : 0);
-  while (slots > 1 && c.streams * (batch_bytes + slots * per_slot) > c.hbm_budget) slots /= 2;
-  if (c.streams * (batch_bytes + slots * per_slot) > c.hbm_budget)
-    return fail(ANN_EBUDGET, "hbm_budget %lld too small for one slot per stream", (long long)c.hbm_budget);
+  if (!s->cfg.idle_us) s->cfg.idle_us = 2000;
+  s->R = c.max_inflight;
+  P.nq = c.max_inflight;
+  int64_t slots = pick_slots(ix, P, c.slots);
+  const int64_t per_slot = slot_bytes(ix->n) + (P.glist ? (int64_t)P.ef_cap * 16 : 0);
+  while (slots > 1 && slots * per_slot > c.hbm_budget) slots /= 2;
+  if (slots * per_slot > c.hbm_budget)
+    return fail(ANN_EBUDGET, "hbm_budget %lld too small for one slot", (long long)c.hbm_budget);
   s->slots = slots;
-  s->proto = proto;
   HIP_OR_RETURN(hipSetDevice(ix->device), "hipSetDevice");
-  s->lanes.resize(c.streams);
-  for (Lane& L : s->lanes) {
-    HIP_OR_RETURN(hipStreamCreateWithFlags(&L.st, hipStreamNonBlocking), "hipStreamCreate");
-    HIP_OR_RETURN(hipEventCreateWithFlags(&L.ev, hipEventDisableTiming), "hipEventCreate");
-    if ((rc = ensure_workspace(ix, L.ws, slots, proto.glist ? proto.ef_cap : 0))) {
-      s->free_lanes();
-      return rc;
-    }
-    const size_t nb = (size_t)max_batch;
-    HIP_OR_RETURN(hipMalloc((void**)&L.dq, sizeof(float) * nb * ix->d), "hipMalloc");
-    HIP_OR_RETURN(hipMalloc((void**)&L.dk, sizeof(int32_t) * nb), "hipMalloc");
-    HIP_OR_RETURN(hipMalloc((void**)&L.def, sizeof(int32_t) * nb), "hipMalloc");
-    HIP_OR_RETURN(hipMalloc((void**)&L.dids, sizeof(int64_t) * nb * c.k_max), "hipMalloc");
-    HIP_OR_RETURN(hipMalloc((void**)&L.dd, sizeof(float) * nb * c.k_max), "hipMalloc");
-    HIP_OR_RETURN(hipMalloc((void**)&L.dstat, sizeof(int32_t) * nb), "hipMalloc");
-    HIP_OR_RETURN(hipHostMalloc((void**)&L.hq, sizeof(float) * nb * ix->d, hipHostMallocDefault), "hipHostMalloc");
-    HIP_OR_RETURN(hipHostMalloc((void**)&L.hk, sizeof(int32_t) * nb, hipHostMallocDefault), "hipHostMalloc");
-    HIP_OR_RETURN(hipHostMalloc((void**)&L.hef, sizeof(int32_t) * nb, hipHostMallocDefault), "hipHostMalloc");
-    HIP_OR_RETURN(hipHostMalloc((void**)&L.hids, sizeof(int64_t) * nb * c.k_max, hipHostMallocDefault), "hipHostMalloc");
-    HIP_OR_RETURN(hipHostMalloc((void**)&L.hd, sizeof(float) * nb * c.k_max, hipHostMallocDefault), "hipHostMalloc");
-    HIP_OR_RETURN(hipHostMalloc((void**)&L.hstat, sizeof(int32_t) * nb, hipHostMallocDefault), "hipHostMalloc");
-    HIP_OR_RETURN(hipMalloc((void**)&L.dnq, sizeof(int32_t)), "hipMalloc");
-    HIP_OR_RETURN(hipHostMalloc((void**)&L.hnq, sizeof(int32_t), hipHostMallocDefault), "hipHostMalloc");
+  int rate_khz = 0;
+  if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, ix->device) == hipSuccess &&
+      rate_khz > 0)
+    s->clock_hz = 1e3 * rate_khz;
+  HIP_OR_RETURN(hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking), "hipStreamCreate");
+  HIP_OR_RETURN(hipEventCreateWithFlags(&s->ev, hipEventDisableTiming), "hipEventCreate");
+  if ((rc = ensure_workspace(ix, s->ws, slots, P.glist ? P.ef_cap : 0))) { s->release(); return rc; }
+  // the ring: one pinned, coherent host block
+  const size_t Rn = (size_t)s->R, d = (size_t)ix->d, km = (size_t)c.k_max;
+  size_t off = 0;
+  auto carve = [&](size_t bytes) { const size_t o = off; off += (bytes + 63) & ~size_t(63); return o; };
+  const size_t o_tail = carve(8), o_stop = carve(4), o_q = carve(4 * Rn * d), o_k = carve(4 * Rn),
+               o_ef = carve(4 * Rn), o_ids = carve(8 * Rn * km), o_d = carve(4 * Rn * km),
+               o_status = carve(4 * Rn), o_done = carve(8 * Rn), o_ts = carve(8 * Rn),
+               o_td = carve(8 * Rn), o_sv = carve(4 * Rn);
+  if (hipHostMalloc(&s->hblock, off, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+    s->hblock = nullptr;
+    s->release();
+    return fail(ANN_ENOMEM, "pinned ring of %zu bytes", off);
   }
-  s->cfg.max_batch = (int32_t)max_batch;
-  for (Lane& L : s->lanes)
-    if ((rc = s->capture(L))) { s->free_lanes(); return rc; }
+  std::memset(s->hblock, 0, off);
+  void* dblock = nullptr;
+  if (hipHostGetDevicePointer(&dblock, s->hblock, 0) != hipSuccess) {
+    s->release();
+    return fail(ANN_EHIP, "hipHostGetDevicePointer");
+  }
+  char* hb = (char*)s->hblock;
+  char* db = (char*)dblock;
+  s->h_tail = (uint64_t*)(hb + o_tail);
+  s->h_stop = (uint32_t*)(hb + o_stop);
+  s->h_q = (float*)(hb + o_q);
+  s->h_k = (int32_t*)(hb + o_k);
+  s->h_ef = (int32_t*)(hb + o_ef);
+  s->h_ids = (int64_t*)(hb + o_ids);
+  s->h_d = (float*)(hb + o_d);
+  s->h_status = (int32_t*)(hb + o_status);
+  s->h_done = (uint64_t*)(hb + o_done);
+  s->h_tstart = (uint64_t*)(hb + o_ts);
+  s->h_tdone = (uint64_t*)(hb + o_td);
+  s->h_served = (int32_t*)(hb + o_sv);
+  // head, mirror, last poll and stop, 256 bytes apart (separate cache lines)
+  if (hipMalloc((void**)&s->d_ctl, 1024) != hipSuccess) { s->d_ctl = nullptr; s->release(); return fail(ANN_ENOMEM, "server control block"); }
+  HIP_OR_RETURN(hipMemset(s->d_ctl, 0, 1024), "hipMemset");
+  s->entry_seq.assign(Rn, -1);
+  s->entry_req.resize(Rn);
+  // kernel parameters: the batch is the ring
+  P.nq = s->R;
+  P.queries = (const float*)(db + o_q);
+  P.k_arr = (const int32_t*)(db + o_k);
+  P.ef_arr = (const int32_t*)(db + o_ef);
+  P.out_ids = (int64_t*)(db + o_ids);
+  P.out_dists = (float*)(db + o_d);
+  P.out_status = (int32_t*)(db + o_status);
+  bind_workspace(P, s->ws);
+  RingArgs& r = P.ring;
+  r.cap = s->R;
+  r.host_tail = (const uint64_t*)(db + o_tail);
+  r.host_stop = (const uint32_t*)(db + o_stop);
+  r.head = s->d_ctl;
+  r.mirror = s->d_ctl + 32;
+  r.last_poll = s->d_ctl + 64;
+  r.dev_stop = (uint32_t*)(s->d_ctl + 96);
+  r.done = (uint64_t*)(db + o_done);
+  r.t_start = (uint64_t*)(db + o_ts);
+  r.t_done = (uint64_t*)(db + o_td);
+  r.served_by = (int32_t*)(db + o_sv);
+  r.idle_ticks = (uint64_t)(s->clock_hz * 1e-6 * s->cfg.idle_us);
+  r.poll_ticks = std::max<uint64_t>(1, (uint64_t)(s->clock_hz * 1e-6 * kPollUs));
+  r.idle_spins = 64 + s->cfg.idle_us / 3;
+  s->P = P;
   ann_server* raw = s.get();
   s->th = std::thread([raw] { raw->loop(); });
   *out = s.release();
@@ -330,6 +362,7 @@ int ann_server_submit(ann_server* s, const ann_request* r) {
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) return fail(ANN_EINVAL, "server is stopping");
+    if (s->loop_error) return fail(s->loop_error, "the server's kernel failed earlier (code %d)", s->loop_error);
     if ((int64_t)s->queue.size() >= s->cfg.queue_cap) return fail(ANN_EAGAIN, "queue full");
     s->queue.push_back(std::move(q));
   }
@@ -351,9 +384,25 @@ int ann_server_poll(ann_server* s, ann_completion* out, int32_t max) {
     o.t_submit = c.t_submit;
     o.t_start = c.t_start;
     o.t_done = c.t_done;
+    o.d_start = c.d_start;
+    o.d_done = c.d_done;
+    o.slot = c.slot;
+    o.reserved = 0;
     s->done.pop_front();
   }
   return n;
+}
+
+int ann_server_info(const ann_server* s, ann_server_state* out) {
+  if (!s || !out) return fail(ANN_EINVAL, "NULL argument");
+  ann_server* m = const_cast<ann_server*>(s);
+  std::lock_guard<std::mutex> lk(m->mu);
+  out->slots = (int32_t)s->slots;
+  out->ring = (int32_t)s->R;
+  out->waves_per_query = s->P.waves_per_query;
+  out->lanes_per_row = s->P.lanes_per_row;
+  out->queued = (int64_t)s->queue.size();
+  return ANN_OK;
 }
 
 int ann_server_destroy(ann_server* s) {
@@ -365,7 +414,7 @@ int ann_server_destroy(ann_server* s) {
   }
   s->cv.notify_all();
   if (s->th.joinable()) s->th.join();
-  s->free_lanes();
+  s->release();
   const int err = s->loop_error;
   delete s;
   return err;

@@ -33,7 +33,7 @@ def test_struct_layouts_match_the_c_header(tmp_path):
     structs = {"ann_index_desc": ann.AnnIndexDesc, "ann_batch": ann.AnnBatch,
                "ann_launch_cfg": ann.AnnLaunchCfg, "ann_info": ann.AnnIndexInfo,
                "ann_server_cfg": ann.AnnServerCfg, "ann_request": ann.AnnRequest,
-               "ann_completion": ann.AnnCompletion, "ann_ivf_batch": ann.AnnIvfBatch}
+               "ann_completion": ann.AnnCompletion, "ann_server_state": ann.AnnServerState, "ann_ivf_batch": ann.AnnIvfBatch}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ann.h"', 'int main(void) {']
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')

@@ -78,8 +78,7 @@ def test_serving_mix_1m_x_96():
     try:
         n = 1500
         t_arr, qidx, ks, efs = synth.arrivals(3, n, 20000.0, n_pool=Q.shape[0])
-        srv = ann.Server(ix, mode="f16", rerank=40, max_inflight=4096, max_batch=512, streams=3,
-                         k_max=100, ef_max=512)
+        srv = ann.Server(ix, mode="f16", rerank=40, max_inflight=4096, k_max=100, ef_max=512)
         got = {}
         try:
             t0 = time.perf_counter()
