@@ -1259,45 +1259,45 @@ __device__ __forceinline__ void run_query(const SearchParams& p, const Lds& s, P
 #define ANN_OCCUPANCY
 #endif
 
-// Claims the next published request of a server's ring (thread 0 of a
-// workgroup): its sequence number, or -1 when the host asks the kernel to end
-// or when nothing has been published for idle_ticks.  Every path of the wait
-// ends: the idle clock runs unless new requests keep arriving.
-__device__ int64_t ring_claim(const RingArgs& r) {
-  uint64_t seen = ~0ull;
-  uint64_t t_idle = (uint64_t)wall_clock64();
-  int64_t spins = 0;
-  while (true) {
-    if (__hip_atomic_load(r.dev_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return -1;
-    const uint64_t now = (uint64_t)wall_clock64();
-    uint64_t lp = __hip_atomic_load(r.last_poll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (now - lp >= r.poll_ticks &&
-        __hip_atomic_compare_exchange_strong(r.last_poll, &lp, now, __ATOMIC_RELAXED,
-                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-      // this workgroup is the poller until poll_ticks have passed
-      const uint64_t ht = __hip_atomic_load(r.host_tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
-      __hip_atomic_fetch_max(r.mirror, ht, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      if (__hip_atomic_load(r.host_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))
-        __hip_atomic_store(r.dev_stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    const uint64_t tail = __hip_atomic_load(r.mirror, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    if (tail != seen) { seen = tail; t_idle = now; spins = 0; }
-    uint64_t h = __hip_atomic_load(r.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (h < tail) {
-      if (__hip_atomic_compare_exchange_strong(r.head, &h, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT)) {
-        // the host wrote the entry before publishing it: read it fresh
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
-        return (int64_t)h;
-      }
-      continue;
-    }
-    if (now - t_idle > r.idle_ticks || ++spins > r.idle_spins) return -1;
-    // about 7 us between looks: the waiting slots' reads of the control
-    // words stay a small load on the L2
-    __builtin_amdgcn_s_sleep(127);
-    __builtin_amdgcn_s_sleep(127);
+// One step of waiting for a request of a server's ring, by thread 0 of a
+// workgroup: straight-line code (no loop: a loop that only thread 0 runs
+// would sit in divergent control flow next to the workgroup barriers of the
+// caller's loop).  Returns the claimed sequence number, kRingWait to wait and
+// try again, kRingRetry to try again at once (another slot took the request
+// this one aimed at), or kRingEnd when the host asked the kernel to end or
+// nothing has been published for idle_ticks (idle_spins waits).
+constexpr int64_t kRingWait = -2, kRingRetry = -3, kRingEnd = -1;
+
+struct RingWait {
+  uint64_t seen;     // the last tail seen
+  uint64_t t_idle;   // device clock when it was first seen
+  int64_t spins;     // waits since then
+};
+
+__device__ __forceinline__ int64_t ring_step(const RingArgs& r, RingWait& w) {
+  if (__hip_atomic_load(r.dev_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return kRingEnd;
+  const uint64_t now = (uint64_t)wall_clock64();
+  uint64_t lp = __hip_atomic_load(r.last_poll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (now - lp >= r.poll_ticks &&
+      __hip_atomic_compare_exchange_strong(r.last_poll, &lp, now, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT)) {
+    // this workgroup reads the host's tail for everyone until poll_ticks pass
+    const uint64_t ht = __hip_atomic_load(r.host_tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_fetch_max(r.mirror, ht, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (__hip_atomic_load(r.host_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))
+      __hip_atomic_store(r.dev_stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+  const uint64_t tail = __hip_atomic_load(r.mirror, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+  if (tail != w.seen) { w.seen = tail; w.t_idle = now; w.spins = 0; }
+  uint64_t h = __hip_atomic_load(r.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (h < tail) {
+    if (__hip_atomic_compare_exchange_strong(r.head, &h, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT))
+      return (int64_t)h;
+    return kRingRetry;
+  }
+  if (now - w.t_idle > r.idle_ticks || ++w.spins > r.idle_spins) return kRingEnd;
+  return kRingWait;
 }
 
 template <class Policy, bool GLIST>
@@ -1313,24 +1313,36 @@ __global__ void __launch_bounds__(512) ANN_OCCUPANCY search_kernel(SearchParams 
     nq = nd < 0 ? 0 : nd < p.nq ? nd : p.nq;
   }
   if (p.ring.cap > 0) {
-    // server: one request of the ring at a time
-    const RingArgs& r = p.ring;
+    // server: one request of the ring at a time.  Every loop here is left by
+    // all threads together (the decisions come from LDS after a barrier).
+    const RingArgs r = p.ring;
+    RingWait w{~0ull, (uint64_t)wall_clock64(), 0};
     while (true) {
-      if (threadIdx.x == 0) {
-        const int64_t seq = ring_claim(r);
-        s.ctl[CTL_QUERY] = seq < 0 ? -1 : (int)(seq % r.cap);
-        s.ctl[CTL_SEQ_LO] = (int)(uint32_t)(uint64_t)seq;
-        s.ctl[CTL_SEQ_HI] = (int)(uint32_t)((uint64_t)seq >> 32);
-        if (seq >= 0) r.t_start[seq % r.cap] = (uint64_t)wall_clock64();
+      int64_t seq;
+      while (true) {
+        if (threadIdx.x == 0) {
+          const int64_t got = ring_step(r, w);
+          s.ctl[CTL_SEQ_LO] = (int)(uint32_t)(uint64_t)got;
+          s.ctl[CTL_SEQ_HI] = (int)(uint32_t)((uint64_t)got >> 32);
+        }
+        __syncthreads();
+        seq = (int64_t)(((uint64_t)(uint32_t)uniform_int(s.ctl[CTL_SEQ_HI]) << 32) |
+                        (uint32_t)uniform_int(s.ctl[CTL_SEQ_LO]));
+        __syncthreads();
+        if (seq != kRingWait && seq != kRingRetry) break;
+        if (seq == kRingWait) {
+          // about 7 us between looks: the waiting slots' reads of the
+          // control words stay a small load on the L2
+          __builtin_amdgcn_s_sleep(127);
+          __builtin_amdgcn_s_sleep(127);
+        }
       }
-      __syncthreads();
-      const int pos = uniform_int(s.ctl[CTL_QUERY]);
-      const uint64_t seq = ((uint64_t)(uint32_t)s.ctl[CTL_SEQ_HI] << 32) | (uint32_t)s.ctl[CTL_SEQ_LO];
-      __syncthreads();
-      if (pos < 0) break;
+      if (seq < 0) break;
+      const int64_t pos = seq % r.cap;
       // every wave reads the entry the host wrote before publishing it
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
-      run_query<Policy, GLIST>(p, s, pol, slot, (int64_t)pos);
+      if (threadIdx.x == 0) r.t_start[pos] = (uint64_t)wall_clock64();
+      run_query<Policy, GLIST>(p, s, pol, slot, pos);
       // the results (in host memory) are visible before the completion flag
       __threadfence_system();
       __syncthreads();
@@ -1338,8 +1350,10 @@ __global__ void __launch_bounds__(512) ANN_OCCUPANCY search_kernel(SearchParams 
         r.t_done[pos] = (uint64_t)wall_clock64();
         r.served_by[pos] = slot;
         __threadfence_system();
-        __hip_atomic_store(&r.done[pos], seq + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&r.done[pos], (uint64_t)seq + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
       }
+      // thread 0 has stored the flag before the next round's barrier
+      __syncthreads();
     }
     return;
   }
