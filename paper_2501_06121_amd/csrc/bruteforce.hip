@@ -440,17 +440,61 @@ static size_t bruteforce_scratch_bytes(int64_t n, int64_t nq, int nranges) {
 
 using namespace ann;
 
-extern "C" int ann_bruteforce(const ann_index* cix, const float* queries, int64_t nq, int32_t k,
-                              int64_t* out_ids, float* out_dists, int32_t* out_certified,
-                              void* stream) {
-  if (!cix) return fail(ANN_EINVAL, "index is NULL");
-  ann_index* ix = const_cast<ann_index*>(cix);
+namespace {
+
+// Checks shared by both entry points.
+int bf_check(const ann_index* ix, const float* queries, int64_t nq, int32_t k, const int64_t* out_ids,
+             const float* out_dists) {
+  if (!ix) return fail(ANN_EINVAL, "index is NULL");
   if (!ix->x_f32) return fail(ANN_EUNSUP, "brute force needs the FP32 rows");
   if (k < 1 || k > KC - kRescore) return fail(ANN_EINVAL, "k %d outside [1, %d]", k, KC - kRescore);
   if (ix->d % 4 != 0) return fail(ANN_EUNSUP, "brute force needs d %% 4 == 0 (d=%d)", ix->d);
   if (nq < 0) return fail(ANN_EINVAL, "nq < 0");
+  if (nq > 0 && (!queries || !out_ids || !out_dists)) return fail(ANN_EINVAL, "NULL pointer");
+  return ANN_OK;
+}
+
+// The three kernels of one call, with the row norms (x2, written first when
+// norms is set) and the candidate lists (ckey, cid) at the given addresses.
+int bf_launch(const ann_index* ix, const float* queries, int64_t nq, int32_t k, int64_t* out_ids,
+              float* out_dists, int32_t* out_certified, hipStream_t st, int nranges, float* x2,
+              float* ckey, int32_t* cid, bool norms) {
+  if (norms) {
+    hipLaunchKernelGGL(bf_norms, dim3((unsigned)ix->n), dim3(64), 0, st, ix->x_f32, ix->n, ix->d, x2);
+    HIP_OR_RETURN(hipGetLastError(), "bf_norms launch");
+  }
+  BfParams p;
+  p.X = ix->x_f32; p.x2 = x2; p.n = ix->n; p.d = ix->d; p.metric = ix->metric;
+  p.Q = queries; p.nq = nq; p.nranges = nranges;
+  p.rows_per_range = (ix->n + nranges - 1) / nranges;
+  // bf_finish re-scores the best k + 16 of the merged lists and certifies
+  // them against the next one, so each range needs its exact best k + 17
+  // only: rows that do not beat the (k + 17)-th entry of their range's list
+  // are not inserted (entries further down may then be stale).
+  p.admit = std::min(KC, k + kRescore + 1);
+  p.cand_key = ckey; p.cand_id = cid;
+  const dim3 grid((unsigned)((nq + BM - 1) / BM), (unsigned)nranges);
+  hipLaunchKernelGGL(bf_tiles, grid, dim3(256), 0, st, p);
+  HIP_OR_RETURN(hipGetLastError(), "bf_tiles launch");
+  BfFinish f;
+  f.X = ix->x_f32; f.n = ix->n; f.d = ix->d; f.metric = ix->metric; f.Q = queries; f.nq = nq;
+  f.nranges = nranges; f.cand_key = ckey; f.cand_id = cid; f.k = k;
+  f.xmax = ix->xmax; f.x2max = ix->x2max;
+  f.out_ids = out_ids; f.out_dists = out_dists; f.out_certified = out_certified;
+  hipLaunchKernelGGL(bf_finish, dim3((unsigned)nq), dim3(64), 0, st, f);
+  HIP_OR_RETURN(hipGetLastError(), "bf_finish launch");
+  return ANN_OK;
+}
+
+}  // namespace
+
+extern "C" int ann_bruteforce(const ann_index* cix, const float* queries, int64_t nq, int32_t k,
+                              int64_t* out_ids, float* out_dists, int32_t* out_certified,
+                              void* stream) {
+  int rc = bf_check(cix, queries, nq, k, out_ids, out_dists);
+  if (rc) return rc;
   if (nq == 0) return ANN_OK;
-  if (!queries || !out_ids || !out_dists) return fail(ANN_EINVAL, "NULL pointer");
+  ann_index* ix = const_cast<ann_index*>(cix);
   std::lock_guard<std::mutex> lock(ix->mu);
   HIP_OR_RETURN(hipSetDevice(ix->device), "hipSetDevice");
   hipStream_t st = stream ? (hipStream_t)stream : ix->stream;
@@ -477,31 +521,10 @@ extern "C" int ann_bruteforce(const ann_index* cix, const float* queries, int64_
   float* x2 = (float*)base;
   float* ckey = (float*)(base + (((size_t)ix->n * 4 + 255) & ~size_t(255)));
   int32_t* cid = (int32_t*)(ckey + (size_t)nq * nranges * KC);
-  if (!ix->bf_norms_ready) {
-    hipLaunchKernelGGL(bf_norms, dim3((unsigned)ix->n), dim3(64), 0, st, ix->x_f32, ix->n, ix->d, x2);
-    HIP_OR_RETURN(hipGetLastError(), "bf_norms launch");
-    ix->bf_norms_ready = true;
-  }
-  BfParams p;
-  p.X = ix->x_f32; p.x2 = x2; p.n = ix->n; p.d = ix->d; p.metric = ix->metric;
-  p.Q = queries; p.nq = nq; p.nranges = nranges;
-  p.rows_per_range = (ix->n + nranges - 1) / nranges;
-  // bf_finish re-scores the best k + 16 of the merged lists and certifies
-  // them against the next one, so each range needs its exact best k + 17
-  // only: rows that do not beat the (k + 17)-th entry of their range's list
-  // are not inserted (entries further down may then be stale).
-  p.admit = std::min(KC, k + kRescore + 1);
-  p.cand_key = ckey; p.cand_id = cid;
-  const dim3 grid((unsigned)((nq + BM - 1) / BM), (unsigned)nranges);
-  hipLaunchKernelGGL(bf_tiles, grid, dim3(256), 0, st, p);
-  HIP_OR_RETURN(hipGetLastError(), "bf_tiles launch");
-  BfFinish f;
-  f.X = ix->x_f32; f.n = ix->n; f.d = ix->d; f.metric = ix->metric; f.Q = queries; f.nq = nq;
-  f.nranges = nranges; f.cand_key = ckey; f.cand_id = cid; f.k = k;
-  f.xmax = ix->xmax; f.x2max = ix->x2max;
-  f.out_ids = out_ids; f.out_dists = out_dists; f.out_certified = out_certified;
-  hipLaunchKernelGGL(bf_finish, dim3((unsigned)nq), dim3(64), 0, st, f);
-  HIP_OR_RETURN(hipGetLastError(), "bf_finish launch");
+  rc = bf_launch(ix, queries, nq, k, out_ids, out_dists, out_certified, st, nranges, x2, ckey, cid,
+                 !ix->bf_norms_ready);
+  if (rc) return rc;
+  ix->bf_norms_ready = true;
   HIP_OR_RETURN(hipEventRecord(ix->bf_done, st), "hipEventRecord");
   ix->bf_used = true;
   if (!stream) HIP_OR_RETURN(hipStreamSynchronize(st), "brute force");
