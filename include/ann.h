@@ -406,6 +406,23 @@ int ann_plan_free(ann_plan* plan);
 int ann_bruteforce(const ann_index* ix, const float* queries, int64_t nq, int32_t k,
                    int64_t* out_ids, float* out_dists, int32_t* out_certified, void* stream);
 
+/*
+ * ann_bruteforce with no device allocation, for callers that cannot
+ * allocate memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, results and errors as
+ * ann_bruteforce, bit for bit.  Its scratch (the row norms and the candidate
+ * lists: 4 n + 512 nq r bytes, each rounded up to 256, where r is the
+ * number of row ranges the scan splits the rows into, at most 32) lives in
+ * a fixed device array of ANN_NOALLOC_SCRATCH_BYTES that each GPU the
+ * library runs on holds until the process ends; a call whose scratch would
+ * not fit returns ANN_EBUDGET (split the batch).  Every call on one GPU
+ * uses that GPU's one array: calls that overlap on a GPU (other streams,
+ * other threads, other indexes) race and must be ordered by the caller.
+ */
+#define ANN_NOALLOC_SCRATCH_BYTES (32 << 20)
+int ann_bruteforce_noalloc(const ann_index* ix, const float* queries, int64_t nq, int32_t k,
+                           int64_t* out_ids, float* out_dists, int32_t* out_certified, void* stream);
+
 /* ---- HNSW construction on the device ------------------------------------- */
 
 /*

@@ -110,6 +110,7 @@ SIGNATURES = {
     "ann_plan_info": ([P, P], C.c_int),
     "ann_plan_free": ([P], C.c_int),
     "ann_bruteforce": ([P, P, I64, I32, P, P, P, P], C.c_int),
+    "ann_bruteforce_noalloc": ([P, P, I64, I32, P, P, P, P], C.c_int),
     "ann_pq_train": ([P, I64, I32, P, I64, P, I32, I32, I32, P, P, P], C.c_int),
     "ann_pq_encode": ([P, I64, I32, P, I32, I32, P, P], C.c_int),
     "ann_hnsw_build": ([P, I64, I32, I32, I32, I32, P, I64, C.c_double, I64, P, P], C.c_int),

@@ -530,3 +530,65 @@ extern "C" int ann_bruteforce(const ann_index* cix, const float* queries, int64_
   if (!stream) HIP_OR_RETURN(hipStreamSynchronize(st), "brute force");
   return ANN_OK;
 }
+
+// ---- the variant that allocates nothing ------------------------------------
+//
+// Its scratch (row norms and candidate lists) is a file-scope device array,
+// one per GPU the library runs on, held until the process ends.  In host
+// code `bf_static_scratch` names a host-side stand-in, not device memory:
+// each device's address comes from hipGetSymbolAddress, taken once per
+// device with that device current, and only that address is handed to the
+// kernels.
+namespace {
+
+__device__ __align__(256) char bf_static_scratch[ANN_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices] = {};
+
+// The device address of this device's array (the device must be current).
+int static_scratch(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(ANN_ENODEV, "device %d beyond %d", device, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (!g_static_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(bf_static_scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress (static scratch)");
+    g_static_ptr[device] = p;
+  }
+  *out = g_static_ptr[device];
+  return ANN_OK;
+}
+
+}  // namespace
+
+extern "C" int ann_bruteforce_noalloc(const ann_index* cix, const float* queries, int64_t nq,
+                                      int32_t k, int64_t* out_ids, float* out_dists,
+                                      int32_t* out_certified, void* stream) {
+  int rc = bf_check(cix, queries, nq, k, out_ids, out_dists);
+  if (rc) return rc;
+  if (nq == 0) return ANN_OK;
+  const ann_index* ix = cix;
+  const int nranges = bf_ranges(ix->n, nq, ix->cu_count > 0 ? ix->cu_count : 256);
+  const size_t need = bruteforce_scratch_bytes(ix->n, nq, nranges);
+  if (need > (size_t)ANN_NOALLOC_SCRATCH_BYTES)
+    return fail(ANN_EBUDGET, "%lld queries over %lld rows need %zu bytes of scratch, above the %d "
+                "of ann_bruteforce_noalloc; split the batch", (long long)nq, (long long)ix->n, need,
+                ANN_NOALLOC_SCRATCH_BYTES);
+  HIP_OR_RETURN(hipSetDevice(ix->device), "hipSetDevice");
+  void* base_v = nullptr;
+  if ((rc = static_scratch(ix->device, &base_v))) return rc;
+  hipStream_t st = stream ? (hipStream_t)stream : ix->stream;
+  char* base = (char*)base_v;
+  float* x2 = (float*)base;
+  float* ckey = (float*)(base + (((size_t)ix->n * 4 + 255) & ~size_t(255)));
+  int32_t* cid = (int32_t*)(ckey + (size_t)nq * nranges * KC);
+  // the array keeps whatever the last call left: the norms are recomputed
+  // (L2 only), and every candidate list is written before it is read
+  rc = bf_launch(ix, queries, nq, k, out_ids, out_dists, out_certified, st, nranges, x2, ckey, cid,
+                 ix->metric != METRIC_IP);
+  if (rc) return rc;
+  if (!stream) HIP_OR_RETURN(hipStreamSynchronize(st), "brute force");
+  return ANN_OK;
+}
