@@ -209,7 +209,15 @@ class Timed:
 IvfTimed.run = Timed.run
 
 
-def ivf_row(ann, torch, ivf, mode, Qd, k, nprobe, rerank, stream, gt, d, nlist, steps, warmup):
+def ivf_row(ann, torch, ivf, mode, Qd, k, nprobe, rerank, stream, gt, d, nlist, steps, warmup,
+            traffic=None):
+    """One IVF configuration.  With one query per workgroup every scanned row
+    is read from device memory for its query, so the algorithmic bytes are
+    real HBM bytes and the roofline is the HBM's.  With the shared scan a
+    workgroup reads each probed list once for its 8 queries: the
+    per-query-equivalent bytes then exceed what crosses the HBM interface
+    (the counters measure that), and the bound is the FP32 vector arithmetic
+    of the scoring (2 d flops per scanned row and query)."""
     tm = IvfTimed(ann, torch, ivf, mode, Qd, k, nprobe, rerank, stream)
     ms, _ = tm.run(steps, warmup)
     nq = Qd.shape[0]
@@ -219,28 +227,44 @@ def ivf_row(ann, torch, ivf, mode, Qd, k, nprobe, rerank, stream, gt, d, nlist, 
     evals = float(tm.out["stats"][:, 0].double().sum().item())
     tflops = 2.0 * evals * d / (ms / 1e3) / 1e12
     shared = mode != "pq" and 4 * min(nprobe, nlist) > nlist
-    return {"nprobe": nprobe, "qps": round(nq / (ms / 1e3), 1), "recall@10": rec,
-            "ms_per_step": round(ms, 3),
-            "scan": "8 queries per workgroup share LDS tiles" if shared else "one query per workgroup",
-            "algorithmic_GBps": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
-            "bytes_per_launch": nb, "tflops": round(tflops, 2),
-            "frac_of_fp32_vector_peak": round(tflops / FP32_VECTOR_PEAK, 4)}
+    row = {"nprobe": nprobe, "qps": round(nq / (ms / 1e3), 1), "recall@10": rec,
+           "ms_per_step": round(ms, 3),
+           "scan": "8 queries per workgroup share LDS tiles" if shared else "one query per workgroup",
+           "tflops": round(tflops, 2)}
+    if shared:
+        row["per_query_equivalent_GBps"] = round(gbs, 1)
+        row["roofline"] = {"bound": "alu", "achieved": round(tflops, 2), "peak": FP32_VECTOR_PEAK,
+                           "unit": "TFLOP/s", "frac": round(tflops / FP32_VECTOR_PEAK, 4)}
+    else:
+        row["algorithmic_GBps"] = round(gbs, 1)
+        row["roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    if traffic is not None:
+        row["roofline"]["traffic"] = traffic
+        row["hbm_traffic_GBps"] = round(traffic / (ms / 1e3) / 1e9, 1)
+    return row
 
 
-def serve_latency(ann, ix, Q, k, ef, mode, rerank, qps_peak, seconds=3.0, seed=0, waves=4):
-    """Open-loop Poisson arrivals at half the measured peak; p50/p99 ms.  At half
-    load fewer queries are in flight, so the server gives each query `waves`
-    wavefronts (4: lower latency than the throughput-optimal 2 at this load,
-    measured; 8 no longer keeps up)."""
+def serve_latency(ann, ix, Q, k, ef, mode, rerank, qps_peak, seconds=3.0, seed=0, waves=0):
+    """Open-loop Poisson arrivals at half the measured peak through the
+    server (per-slot admission), each of the first queries once; returns
+    p50/p99 of completion - submission (host clock, ms), the offered rate, and
+    p50/p99 of the device service time (claim to completion on the kernel's
+    own clock).  waves > 0 sets the waves per query of the server's kernel
+    (0: the index's current launch shape)."""
     import synth
-    ann.ann_set_launch(ix, mode, waves_per_query=waves)
+    saved = ann.ann_get_launch(ix, mode)
+    if waves:
+        ann.ann_set_launch(ix, mode, waves_per_query=waves, slots=0,
+                           lanes_per_row=saved["lanes_per_row"])
     rate = max(100.0, 0.5 * qps_peak)
     n_req = int(min(Q.shape[0] * 4, max(200, rate * seconds)))
     t_arr, qidx, _, _ = synth.arrivals(seed, n_req, rate, k_choices=(k,), ef_choices=(ef,),
                                        n_pool=Q.shape[0])
     srv = ann.Server(ix, mode=mode, rerank=rerank, max_inflight=8192, k_max=max(k, 10), ef_max=ef)
-    lat = []
+    lat, svc = [], []
     try:
+        info = srv.info()
         t0 = time.perf_counter()
         i = 0
         done = 0
@@ -252,14 +276,20 @@ def serve_latency(ann, ix, Q, k, ef, mode, rerank, qps_peak, seconds=3.0, seed=0
                 i += 1
             for c in srv.poll():
                 lat.append((c["t_done"] - c["t_submit"]) * 1e3)
+                svc.append((c["d_done"] - c["d_start"]) * 1e3)
                 done += 1
             if i < n_req and t_arr[i] > now:
                 time.sleep(min(2e-4, t_arr[i] - now))
     finally:
         srv.close()
-        ann.ann_set_launch(ix, mode)
-    lat = np.array(lat)
-    return float(np.percentile(lat, 50)), float(np.percentile(lat, 99)), rate
+        ann.ann_set_launch(ix, mode, **{k_: v for k_, v in saved.items()})
+    lat, svc = np.array(lat), np.array(svc)
+    return {"offered_qps": round(rate, 1), "requests": n_req,
+            "p50_ms": round(float(np.percentile(lat, 50)), 2),
+            "p99_ms": round(float(np.percentile(lat, 99)), 2),
+            "service_p50_ms": round(float(np.percentile(svc, 50)), 2),
+            "service_p99_ms": round(float(np.percentile(svc, 99)), 2),
+            "slots": info["slots"], "waves_per_query": info["waves_per_query"]}
 
 
 def serve_mix(ann, torch, n=None, seconds=3.0, rates=(5000, 10000, 20000, 35000, 50000),
@@ -455,7 +485,7 @@ def host_threads():
     return len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
 
 
-def cpu_baseline(g, X, Q, mode, ef, k, rerank, budget_s=15.0, single_s=8.0):
+def cpu_baseline(g, X, Q, mode, ef, k, rerank, budget_s=20.0, single_s=10.0):
     """The oracle's search (same mode, ef, rerank) on a sample of queries, on
     all host threads (OpenMP across queries), and on one thread (the paper's
     setting) for a shorter sample."""
@@ -508,6 +538,15 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the built-in launch shapes instead of tuning them on a sample")
+    ap.add_argument("--tune-nq", type=int, default=3072,
+                    help="queries of the sample the autotuner times each shape on")
+    ap.add_argument("--launch", default=None, metavar="SLOTS,LANES,WAVES",
+                    help="fixed launch shape of the headline mode instead of the autotuner's "
+                         "(for profiler runs: the same shape the bench line reports)")
+    ap.add_argument("--serve-waves", type=int, default=0,
+                    help="waves per query of the serving kernel (0: the tuned/default shape)")
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the headline mode (for profiler runs)")
     ap.add_argument("--build", action="store_true",
@@ -583,9 +622,9 @@ def main():
             for npb in (int(v) for v in a.ivf_sweep.split(",")):
                 row = ivf_row(ann, torch, ivf, mode, Qd, k, npb, rr, stream, gt, d, nlist, 1, 1)
                 pts.append({"nprobe": npb, "recall": row["recall@10"], "qps": row["qps"],
-                            "algorithmic_GBps": row["algorithmic_GBps"]})
+                            "scan": row["scan"], "roofline": row["roofline"]})
                 log(f"ivf sweep {key} nprobe={npb} recall@10={row['recall@10']:.4f} "
-                    f"qps={row['qps']:.0f} {row['algorithmic_GBps']:.0f} GB/s")
+                    f"qps={row['qps']:.0f} {row['roofline']}")
             res[key] = pts
         path = os.path.join(PROFILES, f"{a.workload}_ivf_sweep.json")
         with open(path, "w") as f:
@@ -626,6 +665,24 @@ def main():
     log(f"ef: {a.mode}+rerank {ef}, f32 {ef32} (smallest ef reaching recall@10 0.95 in the sweep, "
         "else the largest ef measured)")
 
+    # launch shapes: tuned on a sample of the queries (results do not depend
+    # on the shape, only the speed does)
+    launch = launch32 = None
+    if a.launch:
+        sl, ln, wv = (int(v) for v in a.launch.split(","))
+        ann.ann_set_launch(ix, a.mode, slots=sl, lanes_per_row=ln, waves_per_query=wv)
+        launch = dict(ann.ann_get_launch(ix, a.mode), tuned_on=None)
+    elif not a.no_autotune and not a.headline_only:
+        for mode, e_, rr in ((a.mode, ef, a.rerank), ("f32", ef32, 0)):
+            t = time.perf_counter()
+            best = ann.ann_autotune(ix, mode, queries=Qd[:a.tune_nq], k=k, ef=e_, rerank=rr)
+            log(f"autotuned {mode} on {min(a.tune_nq, Q.shape[0])} queries in "
+                f"{time.perf_counter() - t:.1f}s: {best}")
+            if mode == a.mode:
+                launch = dict(best, tuned_on=min(a.tune_nq, Q.shape[0]))
+            else:
+                launch32 = dict(best, tuned_on=min(a.tune_nq, Q.shape[0]))
+
     # headline mode
     head = Timed(ann, torch, ix, a.mode, Qd, k, ef, a.rerank, stream)
     ms, wall = head.run(a.steps, a.warmup)
@@ -655,6 +712,44 @@ def main():
     b32 = algorithmic_bytes(st32["stats"].cpu().numpy(), "f32", d, g.M0, k, 0)
     log(f"f32 ef={ef32}: {ms32:.2f} ms/step, {Q.shape[0] / (ms32 / 1e3):.0f} QPS, recall {rec32}")
 
+    # one small batch replayed as a captured graph (ann_plan_*) against the
+    # same batch launched directly: the host cost of a launch
+    captured = None
+    try:
+        nb_, ef_s = 64, 64
+        plan = ann.Plan(ix, a.mode, capacity=nb_, k=k, ef=ef_s, rerank=a.rerank)
+        plan.queries.copy_(Qd[:nb_])
+        torch.cuda.synchronize()
+        reps = 200
+        for _ in range(5):
+            plan.launch(nb_, stream=stream)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            plan.launch(stream=stream)
+        torch.cuda.synchronize()
+        t_graph = (time.perf_counter() - t) / reps
+        qs = Qd[:nb_]
+        out_d = None
+        for _ in range(5):
+            out_d = ann.ann_search_ex(ix, a.mode, queries=qs, k=k, ef=ef_s, rerank=a.rerank,
+                                      stream=stream, out=out_d)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            ann.ann_search_ex(ix, a.mode, queries=qs, k=k, ef=ef_s, rerank=a.rerank,
+                              stream=stream, out=out_d)
+        torch.cuda.synchronize()
+        t_direct = (time.perf_counter() - t) / reps
+        same = bool(torch.equal(plan.ids[:nb_], out_d["ids"]))
+        captured = {"nq": nb_, "ef": ef_s, "graph_us_per_batch": round(t_graph * 1e6, 1),
+                    "direct_us_per_batch": round(t_direct * 1e6, 1), "same_results": same,
+                    "launch": plan.info()}
+        plan.close()
+        log(f"captured batch of {nb_} at ef {ef_s}: {captured}")
+    except ann.AnnError as e:
+        log(f"captured batch skipped: {e}")
+
     # BF16 rows + the same rerank (an extra row beside the headline)
     bf16_row = None
     if not a.no_bf16:
@@ -662,8 +757,12 @@ def main():
         xb = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)   # round to nearest even
         ixb = ann.ann_index_create(g, spec["metric"], d, x_f32=X, x_bf16=xb)
         del xb
+        if launch:
+            ann.ann_set_launch(ixb, "bf16", slots=launch["slots"],
+                               lanes_per_row=launch["lanes_per_row"],
+                               waves_per_query=launch["waves_per_query"])
         tb = Timed(ann, torch, ixb, "bf16", Qd, k, ef, a.rerank, stream)
-        msb, _ = tb.run(1, 1)
+        msb, _ = tb.run(min(a.steps, 5), min(a.warmup, 1))
         recb = recall(tb.out["ids"].cpu().numpy(), gt, k) if gt is not None else None
         stb = tb.step(stats=True)
         torch.cuda.synchronize()
@@ -703,30 +802,32 @@ def main():
             npb, _ = pick_nprobe(ivf_sweep, key)
             if npb is None:
                 continue
-            ivf_rows[key] = ivf_row(ann, torch, ivf, mode, Qd, k, npb, rr, stream, gt, d, nlist,
-                                    a.steps, a.warmup)
+            traffic = None
             tp = os.path.join(PROFILES, f"ivf_{a.workload}_traffic.json")
             if os.path.exists(tp):
                 t = json.load(open(tp))
                 if (t.get("nprobe") == npb and t.get("mode") == mode and t.get("rerank") == rr
                         and t.get("kernel_sha") == ivf_sha()):
-                    ivf_rows[key]["traffic"] = t.get("bytes_per_launch")
+                    traffic = t.get("bytes_per_launch")
+            ivf_rows[key] = ivf_row(ann, torch, ivf, mode, Qd, k, npb, rr, stream, gt, d, nlist,
+                                    a.steps, a.warmup, traffic=traffic)
+            rf = ivf_rows[key]["roofline"]
             log(f"ivf {key} nprobe={npb}: {ivf_rows[key]['qps']:.0f} QPS, recall "
-                f"{ivf_rows[key]['recall@10']}, {ivf_rows[key]['algorithmic_GBps']:.0f} GB/s")
+                f"{ivf_rows[key]['recall@10']}, {rf['achieved']} {rf['unit']} ({rf['bound']}, "
+                f"{rf['frac']:.3f} of peak)")
         if ivf_sweep:
             ivf_rows["nprobe_sweep"] = {k_: [[r["nprobe"], round(r["recall"], 4), round(r["qps"], 1)]
                                              for r in v] for k_, v in ivf_sweep.items()
                                         if isinstance(v, list)}
 
-    p50 = p99 = rate = None
-    p50_32 = p99_32 = rate32 = None
+    serve = serve32 = None
     if not a.no_serve:
         try:
-            p50, p99, rate = serve_latency(ann, ix, Q, k, ef, a.mode, a.rerank, qps)
-            log(f"serving at {rate:.0f} QPS offered: p50 {p50:.2f} ms p99 {p99:.2f} ms")
+            serve = serve_latency(ann, ix, Q, k, ef, a.mode, a.rerank, qps, waves=a.serve_waves)
+            log(f"serving {a.mode}: {serve}")
             qps32 = Q.shape[0] / (ms32 / 1e3)
-            p50_32, p99_32, rate32 = serve_latency(ann, ix, Q, k, ef32, "f32", 0, qps32)
-            log(f"serving f32 at {rate32:.0f} QPS offered: p50 {p50_32:.2f} ms p99 {p99_32:.2f} ms")
+            serve32 = serve_latency(ann, ix, Q, k, ef32, "f32", 0, qps32, waves=a.serve_waves)
+            log(f"serving f32: {serve32}")
         except ann.AnnError as e:
             log(f"serving skipped: {e}")
 
@@ -761,15 +862,19 @@ def main():
                         f"({spec['centres']} clusters, kappa {spec['kappa']}), inner product, "
                         f"HNSW M={spec['M']} efC={spec['efc']}, {Q.shape[0]:,} queries, k={k}",
             "storage": f"{a.mode} rows, fp32 arithmetic, fp32 rerank of {a.rerank}",
+            "launch": launch or ann.ann_get_launch(ix, a.mode),
+            "captured_batch": captured,
             "ef": ef, "recall@10": rec,
             "recall_target_met": (rec is not None and rec >= 0.95),
             "ef_sweep": ({k_: [[r["ef"], round(r["recall"], 4), round(r["qps"], 1)] for r in v]
                           for k_, v in sweep.items() if isinstance(v, list)} if sweep else None),
-            "p50_ms": p50, "p99_ms": p99, "serve_offered_qps": rate,
+            "p50_ms": serve and serve["p50_ms"], "p99_ms": serve and serve["p99_ms"],
+            "serving": serve,
             "f32": {"ef": ef32, "qps": round(Q.shape[0] / (ms32 / 1e3), 1), "recall@10": rec32,
                     "ms_per_step": round(ms32, 3),
                     "algorithmic_GBps": round(b32 / (ms32 / 1e3) / 1e9, 1),
-                    "p50_ms": p50_32, "p99_ms": p99_32, "serve_offered_qps": rate32},
+                    "p50_ms": serve32 and serve32["p50_ms"], "p99_ms": serve32 and serve32["p99_ms"],
+                    "serving": serve32, "launch": launch32},
             "bf16+rerank": bf16_row,
             "cpu_oracle_single_thread": cpu1,
             "wall_s": round(wall, 3),

@@ -143,7 +143,7 @@ struct Lds {
 // it overwritten by the next one.
 enum { CTL_QUERY = 0, CTL_M = 1, CTL_W = 2, CTL_HINT = 3, CTL_VISITED = 4, CTL_VLOG = 5,
        CTL_VLOG_OVF = 6, CTL_FLUSH = 7, CTL_R0 = 8, CTL_M_ODD = 9, CTL_SEQ_LO = 10,
-       CTL_SEQ_HI = 11 };
+       CTL_SEQ_HI = 11, CTL_BACKOFF = 12 };
 
 __device__ Lds carve(char* base, const SearchParams& p) {
   Lds s;
@@ -1145,20 +1145,23 @@ __device__ __forceinline__ void run_query(const SearchParams& p, const Lds& s, P
     if (R > w) R = w;
     nres = R;
     const int nch = p.d / 4;   // FP32 chunks
-    for (int i0 = 4 * wave; i0 < R; i0 += 4 * num_waves()) {
-      // four rows at a time, 64 lanes per row; lane l takes chunks l + 64 t
-      // in ascending t (256 chunks, 1,024 floats, per round)
-      int rid[4];
-      float acc[4];
+    // kRerankRows rows at a time per wave, 64 lanes per row; lane l takes
+    // chunks l + 64 t in ascending t (256 chunks, 1,024 floats, per round).
+    // Two rows keep the loads in flight without raising the register peak of
+    // the kernel (which bounds the waves a compute unit holds).
+    constexpr int kRerankRows = 2;
+    for (int i0 = kRerankRows * wave; i0 < R; i0 += kRerankRows * num_waves()) {
+      int rid[kRerankRows];
+      float acc[kRerankRows];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kRerankRows; ++u) {
         rid[u] = (i0 + u < R) ? (int)(L.id[i0 + u] & kIdMask) : -1;
         acc[u] = 0.0f;
       }
       for (int tb = 0; tb < nch; tb += 256) {
-        uint4 raw[4][4];
+        uint4 raw[kRerankRows][4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kRerankRows; ++u) {
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
             const int g = tb + lane + 64 * t;
@@ -1168,7 +1171,7 @@ __device__ __forceinline__ void run_query(const SearchParams& p, const Lds& s, P
           }
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kRerankRows; ++u) {
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
             const int g = tb + lane + 64 * t;
@@ -1194,7 +1197,7 @@ __device__ __forceinline__ void run_query(const SearchParams& p, const Lds& s, P
         }
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kRerankRows; ++u) {
         const float v = fold_lanes<64>(acc[u]);
         if (lane == 0 && rid[u] >= 0) s.rk[i0 + u] = (p.metric == METRIC_IP) ? -v : v;
       }
@@ -1263,40 +1266,80 @@ __device__ __forceinline__ void run_query(const SearchParams& p, const Lds& s, P
 // workgroup: straight-line code (no loop: a loop that only thread 0 runs
 // would sit in divergent control flow next to the workgroup barriers of the
 // caller's loop).  Returns the claimed sequence number, kRingWait to wait and
-// try again, kRingRetry to try again at once (another slot took the request
-// this one aimed at), or kRingEnd when the host asked the kernel to end or
-// nothing has been published for idle_ticks (idle_spins waits).
+// try again, kRingRetry to try again at once (the claim word changed under
+// this one, or a new request was just seen), or kRingEnd when the kernel is
+// draining or the host asked it to end.
 constexpr int64_t kRingWait = -2, kRingRetry = -3, kRingEnd = -1;
 
 struct RingWait {
   uint64_t seen;     // the last tail seen
-  uint64_t t_idle;   // device clock when it was first seen
-  int64_t spins;     // waits since then
+  uint64_t act;      // the last activity clock seen
+  int64_t spins;     // waits since either changed
+  int backoff;       // pairs of s_sleep 127 before the next look (1 .. 32)
 };
 
-__device__ __forceinline__ int64_t ring_step(const RingArgs& r, RingWait& w) {
-  if (__hip_atomic_load(r.dev_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return kRingEnd;
+__device__ __forceinline__ int64_t ring_step(const RingArgs& r, RingWait& w, int tier) {
+  uint64_t h = __hip_atomic_load(r.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (h & kRingFlags) return kRingEnd;
   const uint64_t now = (uint64_t)wall_clock64();
+  const uint64_t tail = __hip_atomic_load(r.mirror, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (h < tail) {
+    // a waiting workgroup of a lower tier takes it
+    uint32_t lower = 0;
+#pragma unroll
+    for (int t = 0; t < kRingTiers - 1; ++t)
+      if (t < tier) lower += __hip_atomic_load(&r.waiting[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lower > 0) {
+      w.backoff = 1;
+      return kRingWait;
+    }
+    // counted as in flight before the claim, so that no drain can slip
+    // between a successful claim and the count
+    __hip_atomic_fetch_add(r.busy, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (__hip_atomic_compare_exchange_strong(r.head, &h, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT)) {
+      __hip_atomic_fetch_max(r.activity, now, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_sub(&r.waiting[tier], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      w.backoff = 1;
+      return (int64_t)h;
+    }
+    __hip_atomic_fetch_sub(r.busy, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return kRingRetry;
+  }
+  // nothing to claim: read the host's tail if it is this workgroup's turn
+  // (one reader per poll_ticks among the waiting workgroups)
   uint64_t lp = __hip_atomic_load(r.last_poll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (now - lp >= r.poll_ticks &&
       __hip_atomic_compare_exchange_strong(r.last_poll, &lp, now, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT)) {
-    // this workgroup reads the host's tail for everyone until poll_ticks pass
-    const uint64_t ht = __hip_atomic_load(r.host_tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_fetch_max(r.mirror, ht, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    if (__hip_atomic_load(r.host_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))
-      __hip_atomic_store(r.dev_stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t ht = __hip_atomic_load(r.host_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (__hip_atomic_load(r.host_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
+      __hip_atomic_fetch_or(r.head, kRingStop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return kRingEnd;
+    }
+    if (ht > tail) {
+      __hip_atomic_fetch_max(r.mirror, ht, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_max(r.activity, now, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      w.backoff = 1;
+      return kRingRetry;
+    }
   }
-  const uint64_t tail = __hip_atomic_load(r.mirror, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-  if (tail != w.seen) { w.seen = tail; w.t_idle = now; w.spins = 0; }
-  uint64_t h = __hip_atomic_load(r.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (h < tail) {
-    if (__hip_atomic_compare_exchange_strong(r.head, &h, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT))
-      return (int64_t)h;
-    return kRingRetry;
+  if (tail != w.seen) { w.seen = tail; w.spins = 0; w.backoff = 1; }
+  ++w.spins;
+  // the drain test reads two more shared words: every eighth wait only
+  if ((w.spins & 7) == 0) {
+    const uint64_t act = __hip_atomic_load(r.activity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (act != w.act) { w.act = act; w.spins = 0; }
+    if ((now - act > r.idle_ticks || w.spins > r.idle_spins) &&
+        __hip_atomic_load(r.busy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+      // idle with nothing in flight: the whole kernel ends
+      if (__hip_atomic_compare_exchange_strong(r.head, &h, h | kRingDrain, __ATOMIC_RELAXED,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        return kRingEnd;
+      return kRingRetry;
+    }
   }
-  if (now - w.t_idle > r.idle_ticks || ++w.spins > r.idle_spins) return kRingEnd;
+  w.backoff = w.backoff < 32 ? 2 * w.backoff : 32;
   return kRingWait;
 }
 
@@ -1316,32 +1359,46 @@ __global__ void __launch_bounds__(512) ANN_OCCUPANCY search_kernel(SearchParams 
     // server: one request of the ring at a time.  Every loop here is left by
     // all threads together (the decisions come from LDS after a barrier).
     const RingArgs r = p.ring;
-    RingWait w{~0ull, (uint64_t)wall_clock64(), 0};
+    RingWait w{~0ull, ~0ull, 0, 1};
+    const int tier = min((int)blockIdx.x / r.tier_width, kRingTiers - 1);
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(&r.waiting[tier], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     while (true) {
       int64_t seq;
       while (true) {
         if (threadIdx.x == 0) {
-          const int64_t got = ring_step(r, w);
+          const int64_t got = ring_step(r, w, tier);
+          // a workgroup that leaves stops counting as waiting
+          if (got == kRingEnd)
+            __hip_atomic_fetch_sub(&r.waiting[tier], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           s.ctl[CTL_SEQ_LO] = (int)(uint32_t)(uint64_t)got;
           s.ctl[CTL_SEQ_HI] = (int)(uint32_t)((uint64_t)got >> 32);
+          s.ctl[CTL_BACKOFF] = w.backoff;
         }
         __syncthreads();
         seq = (int64_t)(((uint64_t)(uint32_t)uniform_int(s.ctl[CTL_SEQ_HI]) << 32) |
                         (uint32_t)uniform_int(s.ctl[CTL_SEQ_LO]));
+        const int naps = uniform_int(s.ctl[CTL_BACKOFF]);
         __syncthreads();
         if (seq != kRingWait && seq != kRingRetry) break;
         if (seq == kRingWait) {
-          // about 7 us between looks: the waiting slots' reads of the
-          // control words stay a small load on the L2
-          __builtin_amdgcn_s_sleep(127);
-          __builtin_amdgcn_s_sleep(127);
+          // 1 to 32 pairs of the longest sleep (about 6.8 us a pair at
+          // 2.4 GHz): the longer nothing arrives, the rarer the looks
+          for (int i = 0; i < naps; ++i) {
+            __builtin_amdgcn_s_sleep(127);
+            __builtin_amdgcn_s_sleep(127);
+          }
         }
       }
       if (seq < 0) break;
       const int64_t pos = seq % r.cap;
-      // every wave reads the entry the host wrote before publishing it
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
-      if (threadIdx.x == 0) r.t_start[pos] = (uint64_t)wall_clock64();
+      // the entry the host wrote before publishing it is read fresh: one
+      // acquire per request (an acquire invalidates the L2 of this die, so
+      // the waiting slots' looks at the control words are relaxed loads)
+      if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+        r.t_start[pos] = (uint64_t)wall_clock64();
+      }
+      __syncthreads();
       run_query<Policy, GLIST>(p, s, pol, slot, pos);
       // the results (in host memory) are visible before the completion flag
       __threadfence_system();
@@ -1351,6 +1408,8 @@ __global__ void __launch_bounds__(512) ANN_OCCUPANCY search_kernel(SearchParams 
         r.served_by[pos] = slot;
         __threadfence_system();
         __hip_atomic_store(&r.done[pos], (uint64_t)seq + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_fetch_add(&r.waiting[tier], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_sub(r.busy, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       // thread 0 has stored the flag before the next round's barrier
       __syncthreads();

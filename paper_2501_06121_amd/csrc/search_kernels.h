@@ -16,25 +16,56 @@ enum { METRIC_L2 = 0, METRIC_IP = 1 };
 // workgroup at a time copies *host_tail into *mirror every poll_ticks, the
 // others read the mirror (device memory), and a workgroup claims request
 // `seq` by advancing *head from seq to seq + 1.  When a request is done its
-// results are in host memory and done[seq % cap] = seq + 1.  A workgroup
-// stops waiting when *host_stop is set (seen through *dev_stop) or when no
-// request has been published for idle_ticks; the kernel then ends, and the
-// host launches it again for the next request.
+// results are in host memory and done[seq % cap] = seq + 1.
+// The kernel ends as a whole, never one workgroup at a time (that would
+// leave fewer slots for the requests still to come): when nothing has been
+// claimed or published for idle_ticks (or idle_spins waits) and no request
+// is in flight, a waiting workgroup sets kRingDrain in *head, after which no
+// claim can succeed (claims and the drain are compare-and-swaps of the same
+// word) and every workgroup leaves; the host clears the bit before it
+// launches the kernel again.  *host_stop ends it at
+// once for the workgroups that are waiting: the poller that sees it sets
+// kRingStop in *head.
+// Waiting workgroups look at the claim word and the mirror (two relaxed
+// loads; an acquire would invalidate the L2) and back off from about 7 to
+// about 220 us between looks while nothing arrives: hundreds of idle slots
+// reading the same few control words would otherwise load the memory channel
+// that holds them, under the busy slots' row gathers (measured: service
+// times twice as long at half load as at full load before the backoff).
+// Requests are spread over the compute units: workgroup b belongs to tier
+// b / tier_width (tier_width = the compute units, so the dispatch that hands
+// consecutive workgroups to different compute units puts one workgroup of
+// each tier on each), and a workgroup claims only when no workgroup of a
+// lower tier is waiting.  Without that the slots that have just finished a
+// request (and look most often) take the next ones, and the requests pile up
+// on a few compute units.
+constexpr uint64_t kRingDrain = 1ull << 63;
+constexpr uint64_t kRingStop = 1ull << 62;
+constexpr uint64_t kRingFlags = kRingDrain | kRingStop;
+constexpr int kRingTiers = 8;
+
 struct RingArgs {
   int64_t cap;                      // entries; 0: no ring (batch mode)
   const uint64_t* host_tail;        // host memory: requests published
   const uint32_t* host_stop;        // host memory: nonzero asks the kernel to end
-  uint64_t* head;                   // device: requests claimed
+  uint64_t* head;                   // device: requests claimed | kRingDrain | kRingStop
   uint64_t* mirror;                 // device: the last host_tail read
   uint64_t* last_poll;              // device: clock of the last read of host_tail
-  uint32_t* dev_stop;               // device: host_stop as seen by a poller
+  uint64_t* activity;               // device: clock of the last claim or new tail
+  uint32_t* busy;                   // device: requests claimed (or being claimed), not done
+  uint32_t* waiting;                // device [kRingTiers]: workgroups of each tier waiting
+  int32_t tier_width;               // workgroups per tier (the last tier takes the rest)
   uint64_t* done;                   // host memory [cap]: seq + 1 once request seq is done
   uint64_t* t_start;                // host memory [cap]: device clock at claim
   uint64_t* t_done;                 // host memory [cap]: device clock at completion
   int32_t* served_by;               // host memory [cap]: the workgroup that served it
   uint64_t idle_ticks, poll_ticks;  // device clock ticks
-  int64_t idle_spins;               // the same bound counted in waits (about 7 us each)
+  int64_t idle_spins;               // the idle bound counted in waits (at least 6.8 us each)
 };
+
+// Clears the drain bit and restarts the idle clock before the server's
+// kernel is launched again (one thread).
+void ring_rearm(const RingArgs& r, hipStream_t st);
 
 struct SearchParams {
   int mode, metric;

@@ -10,6 +10,15 @@ namespace ann {
 
 __global__ void reset_counter_kernel(int32_t* c) { *c = 0; }
 
+__global__ void ring_rearm_kernel(uint64_t* head, uint64_t* activity) {
+  __hip_atomic_fetch_and(head, ~kRingDrain, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // keeps a stop
+  __hip_atomic_fetch_max(activity, (uint64_t)wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+void ring_rearm(const RingArgs& r, hipStream_t st) {
+  hipLaunchKernelGGL(ring_rearm_kernel, dim3(1), dim3(1), 0, st, r.head, r.activity);
+}
+
 bool dense_shape_supported(int mode, int nchunks, int L) {
   if (L != 16 && L != 32 && L != 64) return false;
   const int cpl = (nchunks + L - 1) / L;

@@ -10,9 +10,9 @@
 // written by the kernel straight into the ring entry (host memory) with a
 // completion flag; the host thread collects them.
 //
-// The kernel ends by itself when nothing has been published for idle_us
-// (or when the server stops); the host thread launches it again when new
-// requests are waiting.  Results do not depend on which slot serves a
+// The kernel ends as a whole when nothing has been claimed or published for
+// idle_us and no request is in flight (or when the server stops); the host
+// thread launches it again when new requests are waiting.  Results do not depend on which slot serves a
 // request or on what else runs: every key is evaluated in the fixed order.
 #include <hip/hip_runtime.h>
 
@@ -82,7 +82,7 @@ struct ann_server {
   uint64_t* h_tstart = nullptr;
   uint64_t* h_tdone = nullptr;
   int32_t* h_served = nullptr;
-  uint64_t* d_ctl = nullptr;         // device: head, mirror, last poll, stop
+  uint64_t* d_ctl = nullptr;         // device: head, mirror, last poll, activity, busy
   std::vector<int64_t> entry_seq;    // request occupying each entry, -1 when free
   std::vector<Req> entry_req;
   uint64_t next_seq = 0;             // requests published
@@ -108,6 +108,8 @@ int ann_server::launch() {
   const void* fn = kernel_symbol(P);
   if (!fn) return fail(ANN_EUNSUP, "no search kernel for the server's mode");
   if (lds > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  ring_rearm(P.ring, st);
+  HIP_OR_RETURN(hipGetLastError(), "ring rearm");
   SearchParams arg = P;
   void* args[] = {&arg};
   HIP_OR_RETURN(hipLaunchKernel(fn, dim3((unsigned)slots), dim3(64 * P.waves_per_query), args, lds, st),
@@ -313,9 +315,10 @@ int ann_server_create(const ann_index* cix, const ann_server_cfg* cfg, ann_serve
   s->h_tstart = (uint64_t*)(hb + o_ts);
   s->h_tdone = (uint64_t*)(hb + o_td);
   s->h_served = (int32_t*)(hb + o_sv);
-  // head, mirror, last poll and stop, 256 bytes apart (separate cache lines)
-  if (hipMalloc((void**)&s->d_ctl, 1024) != hipSuccess) { s->d_ctl = nullptr; s->release(); return fail(ANN_ENOMEM, "server control block"); }
-  HIP_OR_RETURN(hipMemset(s->d_ctl, 0, 1024), "hipMemset");
+  // head, mirror, last poll, activity and busy, 256 bytes apart
+  // (separate cache lines)
+  if (hipMalloc((void**)&s->d_ctl, 2048) != hipSuccess) { s->d_ctl = nullptr; s->release(); return fail(ANN_ENOMEM, "server control block"); }
+  HIP_OR_RETURN(hipMemset(s->d_ctl, 0, 2048), "hipMemset");
   s->entry_seq.assign(Rn, -1);
   s->entry_req.resize(Rn);
   // kernel parameters: the batch is the ring
@@ -334,14 +337,17 @@ int ann_server_create(const ann_index* cix, const ann_server_cfg* cfg, ann_serve
   r.head = s->d_ctl;
   r.mirror = s->d_ctl + 32;
   r.last_poll = s->d_ctl + 64;
-  r.dev_stop = (uint32_t*)(s->d_ctl + 96);
+  r.activity = s->d_ctl + 32 * 4;
+  r.busy = (uint32_t*)(s->d_ctl + 32 * 5);
+  r.waiting = (uint32_t*)(s->d_ctl + 32 * 6);   // kRingTiers counters, one line
+  r.tier_width = std::max(1, ix->cu_count);
   r.done = (uint64_t*)(db + o_done);
   r.t_start = (uint64_t*)(db + o_ts);
   r.t_done = (uint64_t*)(db + o_td);
   r.served_by = (int32_t*)(db + o_sv);
   r.idle_ticks = (uint64_t)(s->clock_hz * 1e-6 * s->cfg.idle_us);
   r.poll_ticks = std::max<uint64_t>(1, (uint64_t)(s->clock_hz * 1e-6 * kPollUs));
-  r.idle_spins = 64 + s->cfg.idle_us / 3;
+  r.idle_spins = 64 + s->cfg.idle_us / 3;   // waits last at least 7 us
   s->P = P;
   ann_server* raw = s.get();
   s->th = std::thread([raw] { raw->loop(); });
