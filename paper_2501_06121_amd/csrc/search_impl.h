@@ -1276,6 +1276,8 @@ struct RingWait {
   uint64_t act;      // the last activity clock seen
   int64_t spins;     // waits since either changed
   int backoff;       // pairs of s_sleep 127 before the next look (1 .. 32)
+  uint64_t defer_h;  // the request this workgroup left to a lower tier
+  uint64_t defer_t;  // since when
 };
 
 __device__ __forceinline__ int64_t ring_step(const RingArgs& r, RingWait& w, int tier) {
@@ -1289,9 +1291,14 @@ __device__ __forceinline__ int64_t ring_step(const RingArgs& r, RingWait& w, int
 #pragma unroll
     for (int t = 0; t < kRingTiers - 1; ++t)
       if (t < tier) lower += __hip_atomic_load(&r.waiting[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // (a lower tier's workgroup may be asleep: after poll_ticks x 10 this
+    // one takes the request itself)
     if (lower > 0) {
-      w.backoff = 1;
-      return kRingWait;
+      if (w.defer_h != h) { w.defer_h = h; w.defer_t = now; }
+      if (now - w.defer_t < 10 * r.poll_ticks) {
+        w.backoff = 1;
+        return kRingWait;
+      }
     }
     // counted as in flight before the claim, so that no drain can slip
     // between a successful claim and the count
@@ -1343,7 +1350,10 @@ __device__ __forceinline__ int64_t ring_step(const RingArgs& r, RingWait& w, int
   return kRingWait;
 }
 
-template <class Policy, bool GLIST>
+// RING: the server's kernel (requests from a ring); otherwise a batch.  Two
+// instantiations, so that the ring's state does not add to the registers of
+// the batch kernel (they bound how many queries a compute unit holds).
+template <class Policy, bool GLIST, bool RING>
 __global__ void __launch_bounds__(512) ANN_OCCUPANCY search_kernel(SearchParams p) {
   extern __shared__ __align__(16) char lds_raw[];
   const Lds s = carve(lds_raw, p);
@@ -1355,11 +1365,11 @@ __global__ void __launch_bounds__(512) ANN_OCCUPANCY search_kernel(SearchParams 
     const int64_t nd = (int64_t)uniform_int(*p.nq_dev);
     nq = nd < 0 ? 0 : nd < p.nq ? nd : p.nq;
   }
-  if (p.ring.cap > 0) {
+  if constexpr (RING) {
     // server: one request of the ring at a time.  Every loop here is left by
     // all threads together (the decisions come from LDS after a barrier).
     const RingArgs r = p.ring;
-    RingWait w{~0ull, ~0ull, 0, 1};
+    RingWait w{~0ull, ~0ull, 0, 1, ~0ull, 0};
     const int tier = min((int)blockIdx.x / r.tier_width, kRingTiers - 1);
     if (threadIdx.x == 0) __hip_atomic_fetch_add(&r.waiting[tier], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     while (true) {
@@ -1391,23 +1401,37 @@ __global__ void __launch_bounds__(512) ANN_OCCUPANCY search_kernel(SearchParams 
       }
       if (seq < 0) break;
       const int64_t pos = seq % r.cap;
-      // the entry the host wrote before publishing it is read fresh: one
-      // acquire per request (an acquire invalidates the L2 of this die, so
-      // the waiting slots' looks at the control words are relaxed loads)
+      // the host's entry into this workgroup's copy: system-scope loads see
+      // what the host wrote before it published the entry, without an
+      // acquire (which would invalidate this die's L2 once per request)
       if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
-        r.t_start[pos] = (uint64_t)wall_clock64();
+        __hip_atomic_store(&r.t_start[pos], (uint64_t)wall_clock64(), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+        ((int32_t*)p.k_arr)[slot] = __hip_atomic_load(&r.e_k[pos], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        ((int32_t*)p.ef_arr)[slot] = __hip_atomic_load(&r.e_ef[pos], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
       }
+      for (int i = threadIdx.x; i < p.d; i += blockDim.x)
+        ((float*)p.queries)[(size_t)slot * p.d + i] =
+            __hip_atomic_load(&r.e_query[(size_t)pos * p.d + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
       __syncthreads();
-      run_query<Policy, GLIST>(p, s, pol, slot, pos);
-      // the results (in host memory) are visible before the completion flag
-      __threadfence_system();
+      run_query<Policy, GLIST>(p, s, pol, slot, slot);
+      // the results out to the host's entry with system-scope stores, which
+      // complete (s_waitcnt) before the completion flag is written
+      for (int i = threadIdx.x; i < p.k_max; i += blockDim.x) {
+        __hip_atomic_store(&r.e_ids[pos * p.k_max + i], p.out_ids[(int64_t)slot * p.k_max + i],
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&r.e_dists[pos * p.k_max + i], p.out_dists[(int64_t)slot * p.k_max + i],
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+      if (threadIdx.x == 0) {
+        __hip_atomic_store(&r.e_status[pos], p.out_status[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&r.t_done[pos], (uint64_t)wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&r.served_by[pos], slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+      __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
       if (threadIdx.x == 0) {
-        r.t_done[pos] = (uint64_t)wall_clock64();
-        r.served_by[pos] = slot;
-        __threadfence_system();
-        __hip_atomic_store(&r.done[pos], (uint64_t)seq + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&r.done[pos], (uint64_t)seq + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         __hip_atomic_fetch_add(&r.waiting[tier], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_sub(r.busy, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
@@ -1432,7 +1456,11 @@ __global__ void __launch_bounds__(512) ANN_OCCUPANCY search_kernel(SearchParams 
 
 template <class Policy>
 inline const void* pick_kernel(const SearchParams& p) {
-  return p.glist ? (const void*)search_kernel<Policy, true> : (const void*)search_kernel<Policy, false>;
+  if (p.ring.cap > 0)
+    return p.glist ? (const void*)search_kernel<Policy, true, true>
+                   : (const void*)search_kernel<Policy, false, true>;
+  return p.glist ? (const void*)search_kernel<Policy, true, false>
+                 : (const void*)search_kernel<Policy, false, false>;
 }
 
 // Kernel for a dense mode: L lanes per row, CPL 16-byte chunks per lane.

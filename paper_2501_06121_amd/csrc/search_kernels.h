@@ -55,6 +55,17 @@ struct RingArgs {
   uint32_t* busy;                   // device: requests claimed (or being claimed), not done
   uint32_t* waiting;                // device [kRingTiers]: workgroups of each tier waiting
   int32_t tier_width;               // workgroups per tier (the last tier takes the rest)
+  // the entries in host memory: read and written with system-scope atomic
+  // loads and stores (coherent per access, so no fence has to invalidate or
+  // write back a whole cache); the search itself runs on a per-workgroup copy
+  // in device memory (SearchParams queries / k_arr / ef_arr / out_*, indexed
+  // by the workgroup)
+  const float* e_query;             // [cap][d]
+  const int32_t* e_k;               // [cap]
+  const int32_t* e_ef;              // [cap]
+  int64_t* e_ids;                   // [cap][k_max]
+  float* e_dists;                   // [cap][k_max]
+  int32_t* e_status;                // [cap]
   uint64_t* done;                   // host memory [cap]: seq + 1 once request seq is done
   uint64_t* t_start;                // host memory [cap]: device clock at claim
   uint64_t* t_done;                 // host memory [cap]: device clock at completion

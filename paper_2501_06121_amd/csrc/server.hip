@@ -83,6 +83,7 @@ struct ann_server {
   uint64_t* h_tdone = nullptr;
   int32_t* h_served = nullptr;
   uint64_t* d_ctl = nullptr;         // device: head, mirror, last poll, activity, busy
+  void* d_stage = nullptr;           // device: each slot's copy of its request and results
   std::vector<int64_t> entry_seq;    // request occupying each entry, -1 when free
   std::vector<Req> entry_req;
   uint64_t next_seq = 0;             // requests published
@@ -231,6 +232,8 @@ void ann_server::release() {
   if (st) (void)hipStreamSynchronize(st);
   ws.release();
   if (d_ctl) (void)hipFree(d_ctl);
+  if (d_stage) (void)hipFree(d_stage);
+  d_stage = nullptr;
   if (hblock) (void)hipHostFree(hblock);
   if (ev) (void)hipEventDestroy(ev);
   if (st) (void)hipStreamDestroy(st);
@@ -268,6 +271,7 @@ int ann_server_create(const ann_index* cix, const ann_server_cfg* cfg, ann_serve
   if (!s->cfg.idle_us) s->cfg.idle_us = 2000;
   s->R = c.max_inflight;
   P.nq = c.max_inflight;
+  P.ring.cap = s->R;       // the occupancy is the server kernel's
   int64_t slots = pick_slots(ix, P, c.slots);
   const int64_t per_slot = slot_bytes(ix->n) + (P.glist ? (int64_t)P.ef_cap * 16 : 0);
   while (slots > 1 && slots * per_slot > c.hbm_budget) slots /= 2;
@@ -321,14 +325,22 @@ int ann_server_create(const ann_index* cix, const ann_server_cfg* cfg, ann_serve
   HIP_OR_RETURN(hipMemset(s->d_ctl, 0, 2048), "hipMemset");
   s->entry_seq.assign(Rn, -1);
   s->entry_req.resize(Rn);
-  // kernel parameters: the batch is the ring
-  P.nq = s->R;
-  P.queries = (const float*)(db + o_q);
-  P.k_arr = (const int32_t*)(db + o_k);
-  P.ef_arr = (const int32_t*)(db + o_ef);
-  P.out_ids = (int64_t*)(db + o_ids);
-  P.out_dists = (float*)(db + o_d);
-  P.out_status = (int32_t*)(db + o_status);
+  // kernel parameters: each slot searches a copy of its request in device
+  // memory (row `slot` of these arrays); the ring entries are in RingArgs
+  const size_t sn = (size_t)slots;
+  size_t so = 0;
+  auto scarve = [&](size_t bytes) { const size_t o = so; so += (bytes + 255) & ~size_t(255); return o; };
+  const size_t s_q = scarve(4 * sn * d), s_k = scarve(4 * sn), s_ef = scarve(4 * sn),
+               s_ids = scarve(8 * sn * km), s_d = scarve(4 * sn * km), s_st = scarve(4 * sn);
+  if (hipMalloc(&s->d_stage, so) != hipSuccess) { s->d_stage = nullptr; s->release(); return fail(ANN_ENOMEM, "server staging"); }
+  char* sb = (char*)s->d_stage;
+  P.nq = slots;
+  P.queries = (const float*)(sb + s_q);
+  P.k_arr = (const int32_t*)(sb + s_k);
+  P.ef_arr = (const int32_t*)(sb + s_ef);
+  P.out_ids = (int64_t*)(sb + s_ids);
+  P.out_dists = (float*)(sb + s_d);
+  P.out_status = (int32_t*)(sb + s_st);
   bind_workspace(P, s->ws);
   RingArgs& r = P.ring;
   r.cap = s->R;
@@ -341,6 +353,12 @@ int ann_server_create(const ann_index* cix, const ann_server_cfg* cfg, ann_serve
   r.busy = (uint32_t*)(s->d_ctl + 32 * 5);
   r.waiting = (uint32_t*)(s->d_ctl + 32 * 6);   // kRingTiers counters, one line
   r.tier_width = std::max(1, ix->cu_count);
+  r.e_query = (const float*)(db + o_q);
+  r.e_k = (const int32_t*)(db + o_k);
+  r.e_ef = (const int32_t*)(db + o_ef);
+  r.e_ids = (int64_t*)(db + o_ids);
+  r.e_dists = (float*)(db + o_d);
+  r.e_status = (int32_t*)(db + o_status);
   r.done = (uint64_t*)(db + o_done);
   r.t_start = (uint64_t*)(db + o_ts);
   r.t_done = (uint64_t*)(db + o_td);
