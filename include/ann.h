@@ -342,10 +342,11 @@ int ann_get_launch(const ann_index* ix, int32_t mode, ann_launch_cfg* out);
  * Times candidate launch shapes on the given batch (as for ann_search_ex;
  * the outputs are written by every run) on the index stream and keeps the
  * fastest for b->mode: lanes per row (16 / 32 / 64 where the mode supports
- * them) x waves per query (1 / 2 / 4 / 8) with slots from the occupancy,
- * then 3/4 and 1/2 of those slots for the best shape.  Each candidate runs
- * twice and the second run is timed.  Shapes whose on-chip memory does not
- * fit are skipped.  beam_buffer and beam_list keep their current values.
+ * them) x waves per query (1 / 2 / 4 / 8) with slots from the occupancy;
+ * then, for the best shape, half and twice its insert buffer (wide beams
+ * only); then 3/4 and 1/2 of its slots.  Each candidate runs twice and the
+ * second run is timed.  Shapes whose on-chip memory does not fit are
+ * skipped.  beam_list keeps its current value.
  * Results are identical for every shape (the arithmetic order is fixed);
  * only speed differs.  The chosen configuration is written to *best when not
  * NULL.  Blocking; ANN_EBUDGET if no shape fits.

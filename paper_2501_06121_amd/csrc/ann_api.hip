@@ -647,7 +647,26 @@ int ann_autotune(ann_index* ix, const ann_batch* b, ann_launch_cfg* best) {
     }
   }
   if (best_ms >= 1e30f) return fail(ANN_EBUDGET, "no launch shape fits this batch");
-  // 2. fewer slots than the occupancy allows (less contention for the
+  // 2. the insert buffer of a wide beam: larger means rarer flushes into the
+  //    sorted list but longer merges into the buffer, for the best shape
+  {
+    ix->cfg[mode] = pick;
+    SearchParams Q;
+    if ((rc = make_params(ix, b, &Q))) return rc;
+    if (Q.wbuf > 0) {
+      for (int wb : {Q.wbuf / 2, Q.wbuf * 2}) {
+        if (wb < 64 || wb > 4096) continue;
+        ann_launch_cfg c = pick;
+        c.beam_buffer = wb;
+        float ms = 0.f;
+        rc = time_cfg(c, &ms);
+        if (rc == ANN_EBUDGET) continue;
+        if (rc) return rc;
+        if (ms < best_ms) { best_ms = ms; pick = c; }
+      }
+    }
+  }
+  // 3. fewer slots than the occupancy allows (less contention for the
   //    caches and the memory system), for the best shape
   {
     ix->cfg[mode] = pick;
