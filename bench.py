@@ -864,7 +864,13 @@ def main():
     tp = os.path.join(PROFILES, f"search_{a.workload}_traffic.json")
     if os.path.exists(tp):
         t = json.load(open(tp))
-        if t.get("ef") == ef and t.get("mode") == a.mode and t.get("kernel_sha") == kernel_sha():
+        shape = None
+        if launch:
+            shape = ",".join(str(launch[f]) for f in ("slots", "lanes_per_row", "waves_per_query",
+                                                      "beam_buffer"))
+        # counters describe one kernel version at one launch shape
+        if (t.get("ef") == ef and t.get("mode") == a.mode and t.get("kernel_sha") == kernel_sha()
+                and t.get("launch") == shape):
             traffic = t.get("bytes_per_launch")
 
     out = {
