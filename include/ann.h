@@ -343,10 +343,11 @@ int ann_get_launch(const ann_index* ix, int32_t mode, ann_launch_cfg* out);
  * the outputs are written by every run) on the index stream and keeps the
  * fastest for b->mode: lanes per row (16 / 32 / 64 where the mode supports
  * them) x waves per query (1 / 2 / 4 / 8) with slots from the occupancy;
- * then, for the best shape, half and twice its insert buffer (wide beams
- * only); then 3/4 and 1/2 of its slots.  Each candidate runs twice and the
- * second run is timed.  Shapes whose on-chip memory does not fit are
- * skipped.  beam_list keeps its current value.
+ * then, for a wide beam (one with an insert buffer), its list in the other
+ * place (LDS or HBM) at every waves-per-query count, and half and twice
+ * the insert buffer of the best shape; then 3/4 and 1/2 of its slots.  Each
+ * candidate runs twice and the second run is timed.  Shapes whose on-chip
+ * memory does not fit are skipped.
  * Results are identical for every shape (the arithmetic order is fixed);
  * only speed differs.  The chosen configuration is written to *best when not
  * NULL.  Blocking; ANN_EBUDGET if no shape fits.

@@ -647,7 +647,27 @@ int ann_autotune(ann_index* ix, const ann_batch* b, ann_launch_cfg* best) {
     }
   }
   if (best_ms >= 1e30f) return fail(ANN_EBUDGET, "no launch shape fits this batch");
-  // 2. the insert buffer of a wide beam: larger means rarer flushes into the
+  // 2. a wide beam's list in the other place (on chip it costs LDS, which
+  //    bounds the queries per compute unit; in HBM it costs a round trip
+  //    per expansion), with every waves-per-query count at the best lanes
+  {
+    ix->cfg[mode] = pick;
+    SearchParams Q;
+    if ((rc = make_params(ix, b, &Q))) return rc;
+    if (Q.wbuf > 0) {
+      for (int nw : {1, 2, 4, 8}) {
+        ann_launch_cfg c = pick;
+        c.beam_list = Q.glist ? ANN_BEAM_LDS : ANN_BEAM_HBM;
+        c.waves_per_query = nw;
+        float ms = 0.f;
+        rc = time_cfg(c, &ms);
+        if (rc == ANN_EBUDGET) continue;
+        if (rc) return rc;
+        if (ms < best_ms) { best_ms = ms; pick = c; }
+      }
+    }
+  }
+  // 3. the insert buffer of a wide beam: larger means rarer flushes into the
   //    sorted list but longer merges into the buffer, for the best shape
   {
     ix->cfg[mode] = pick;
@@ -666,7 +686,7 @@ int ann_autotune(ann_index* ix, const ann_batch* b, ann_launch_cfg* best) {
       }
     }
   }
-  // 3. fewer slots than the occupancy allows (less contention for the
+  // 4. fewer slots than the occupancy allows (less contention for the
   //    caches and the memory system), for the best shape
   {
     ix->cfg[mode] = pick;

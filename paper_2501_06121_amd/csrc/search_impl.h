@@ -1285,12 +1285,12 @@ __device__ __forceinline__ int64_t ring_step(const RingArgs& r, RingWait& w, int
   if (h & kRingFlags) return kRingEnd;
   const uint64_t now = (uint64_t)wall_clock64();
   const uint64_t tail = __hip_atomic_load(r.mirror, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (h < tail) {
-    // a waiting workgroup of a lower tier takes it
-    uint32_t lower = 0;
+  // waiting workgroups of lower tiers: they take the traffic first
+  uint32_t lower = 0;
 #pragma unroll
-    for (int t = 0; t < kRingTiers - 1; ++t)
-      if (t < tier) lower += __hip_atomic_load(&r.waiting[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int t = 0; t < kRingTiers - 1; ++t)
+    if (t < tier) lower += __hip_atomic_load(&r.waiting[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (h < tail) {
     // (a lower tier's workgroup may be asleep: after poll_ticks x 10 this
     // one takes the request itself)
     if (lower > 0) {
@@ -1313,10 +1313,15 @@ __device__ __forceinline__ int64_t ring_step(const RingArgs& r, RingWait& w, int
     __hip_atomic_fetch_sub(r.busy, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return kRingRetry;
   }
-  // nothing to claim: read the host's tail if it is this workgroup's turn
-  // (one reader per poll_ticks among the waiting workgroups)
+  // nothing to claim.  Only the front (the lowest tier with waiting
+  // workgroups) stays responsive: it reads the host's tail when it is its
+  // turn (one reader per poll_ticks) and looks again soon after the ring
+  // moves.  Tiers behind it sleep the longest naps: thousands of workgroups
+  // polling the same few words every few microseconds slow every search in
+  // flight (measured: 5.6 ms instead of 1.0 ms per request).
+  const bool front = lower == 0;
   uint64_t lp = __hip_atomic_load(r.last_poll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (now - lp >= r.poll_ticks &&
+  if (front && now - lp >= r.poll_ticks &&
       __hip_atomic_compare_exchange_strong(r.last_poll, &lp, now, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT)) {
     const uint64_t ht = __hip_atomic_load(r.host_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -1331,7 +1336,7 @@ __device__ __forceinline__ int64_t ring_step(const RingArgs& r, RingWait& w, int
       return kRingRetry;
     }
   }
-  if (tail != w.seen) { w.seen = tail; w.spins = 0; w.backoff = 1; }
+  if (front && tail != w.seen) { w.seen = tail; w.spins = 0; w.backoff = 1; }
   ++w.spins;
   // the drain test reads two more shared words: every eighth wait only
   if ((w.spins & 7) == 0) {
@@ -1346,7 +1351,7 @@ __device__ __forceinline__ int64_t ring_step(const RingArgs& r, RingWait& w, int
       return kRingRetry;
     }
   }
-  w.backoff = w.backoff < 32 ? 2 * w.backoff : 32;
+  w.backoff = front && w.backoff < 32 ? 2 * w.backoff : 32;
   return kRingWait;
 }
 
