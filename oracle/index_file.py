@@ -118,12 +118,15 @@ def read(path):
         raise ValueError("table checksum")
     shapes = _shapes(h)
     out = {}
-    end = _pad(tab_end + 4)
+    end = tab_end + 4
     prev = 0
     for j in range(s):
         i, crc, off, size, zero = struct.unpack_from("<IIQQQ", raw, HEADER + ENTRY * j)
-        if i not in SECTIONS or i <= prev or zero or off % ALIGN or off < end:
+        # each section at the first 64-byte boundary after what precedes it
+        if i not in SECTIONS or i <= prev or zero or off != _pad(end):
             raise ValueError(f"table entry {j}")
+        if any(raw[end:min(off, len(raw))]):
+            raise ValueError(f"padding before table entry {j}")
         name, dt = SECTIONS[i]
         shape = shapes[name]
         if size != int(np.prod(shape)) * np.dtype(dt).itemsize or size == 0:

@@ -200,7 +200,7 @@ int parse(const Mapping& m, ann_index_desc* D, Header* hout) {
   D->max_level = h.max_level; D->entry_point = h.entry_point; D->n_upper_lists = h.n_upper_lists;
   const void* at[kSections + 1] = {};
   int prev = 0;
-  uint64_t end = table_end(h.sections);
+  uint64_t end = tab + 4;   // the table's CRC ends here
   for (uint32_t i = 0; i < h.sections; ++i) {
     const uint8_t* e = b + kHeaderBytes + (size_t)i * kEntryBytes;
     const int id = (int)get<uint32_t>(e);
@@ -209,15 +209,21 @@ int parse(const Mapping& m, ann_index_desc* D, Header* hout) {
     if (id < 1 || id > kSections) return fail(ANN_EFORMAT, "unknown section id %d", id);
     if (id <= prev) return fail(ANN_EFORMAT, "section %s out of order or repeated", section_name(id));
     if (get<uint64_t>(e + 24) != 0) return fail(ANN_EFORMAT, "section %s: reserved field not zero", section_name(id));
-    if (off % kAlign != 0 || off < end)
-      return fail(ANN_EFORMAT, "section %s at offset %llu: misaligned or overlapping", section_name(id),
-                  (unsigned long long)off);
+    // each section starts at the first 64-byte boundary after what precedes
+    // it, with zero bytes in between
+    if (off != align_up(end))
+      return fail(ANN_EFORMAT, "section %s at offset %llu: misaligned or misplaced (expected %llu)", section_name(id),
+                  (unsigned long long)off, (unsigned long long)align_up(end));
     const uint64_t want = expected_size(h, id);
     if (want == 0 || size != want)
       return fail(ANN_EFORMAT, "section %s has %llu bytes, the header implies %llu", section_name(id),
                   (unsigned long long)size, (unsigned long long)want);
     if (off > m.size || size > m.size - off)
       return fail(ANN_EFORMAT, "index file truncated inside section %s", section_name(id));
+    for (uint64_t z = end; z < off; ++z)
+      if (b[z] != 0)
+        return fail(ANN_EFORMAT, "nonzero padding byte at offset %llu before section %s",
+                    (unsigned long long)z, section_name(id));
     if (crc32()(b + off, size) != crc) return fail(ANN_EFORMAT, "section %s checksum mismatch", section_name(id));
     at[id] = b + off;
     prev = id;

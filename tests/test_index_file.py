@@ -161,6 +161,46 @@ def test_truncated_and_padded_files(tmp_path, dense):
     assert code == ann.ANN_EFORMAT and "after the last section" in msg
 
 
+def test_padding_and_section_placement(tmp_path, dense):
+    """Sections start at the first 64-byte boundary after what precedes them,
+    with zero bytes in between: a nonzero padding byte, or a section moved to
+    a later boundary (table and checksums kept valid), is rejected by both
+    readers."""
+    p = tmp_path / "x.idx"
+    oif.write(p, dense["g"], "l2", dense["d"], **dense["arrays"])
+    good = p.read_bytes()
+    s = struct.unpack_from("<I", good, 12)[0]
+    table_end = 128 + 32 * s + 4
+    gaps = [(table_end, min(off for off, _ in sections_of(p).values()))]
+    ends = sorted((off + size, off) for off, size in sections_of(p).values())
+    offs = sorted(off for off, _ in sections_of(p).values())
+    gaps += [(e, nxt) for (e, _), nxt in zip(ends, offs[1:]) if nxt > e]
+    assert any(b > a for a, b in gaps), "the fixture has no padding to damage"
+    for a, b in gaps:
+        if b <= a:
+            continue
+        bad = bytearray(good)
+        bad[a] = 0x5A
+        q = tmp_path / f"pad_{a}.idx"
+        q.write_bytes(bytes(bad))
+        code, msg = code_of(q)
+        assert code == ann.ANN_EFORMAT and "padding" in msg, (a, msg)
+        with pytest.raises(ValueError):
+            oif.read(q)
+    # the last section moved 64 bytes further, the gap zero-filled
+    j = s - 1
+    i, crc, off, size, _ = struct.unpack_from("<IIQQQ", good, 128 + 32 * j)
+    bad = bytearray(good[:off]) + b"\0" * 64 + good[off:off + size]
+    struct.pack_into("<Q", bad, 128 + 32 * j + 8, off + 64)
+    struct.pack_into("<I", bad, 128 + 32 * s, zlib.crc32(bytes(bad[128:128 + 32 * s])))
+    q = tmp_path / "moved.idx"
+    q.write_bytes(bytes(bad))
+    code, msg = code_of(q)
+    assert code == ann.ANN_EFORMAT and "misplaced" in msg, msg
+    with pytest.raises(ValueError):
+        oif.read(q)
+
+
 def test_inconsistent_contents_with_valid_checksums(tmp_path, dense, sparse):
     g = dense["g"]
 
