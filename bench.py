@@ -503,10 +503,11 @@ def host_threads():
     return len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
 
 
-def cpu_baseline(g, X, Q, mode, ef, k, rerank, budget_s=20.0, single_s=10.0):
+def cpu_baseline(g, X, Q, mode, ef, k, rerank, budget_s=20.0, single_s=10.0, exact_s=8.0):
     """The oracle's search (same mode, ef, rerank) on a sample of queries, on
     all host threads (OpenMP across queries), and on one thread (the paper's
-    setting) for a shorter sample."""
+    setting) for a shorter sample; then the same search with EXACT keys (FP64
+    sums rounded once) on all host threads, the oracle's reference mode."""
     import oracle
     g = oracle.Graph(g.n, g.M, g.M0, g.max_level, g.entry, g.levels, g.adj0, g.upper_off,
                      g.upper_adj)
@@ -538,7 +539,18 @@ def cpu_baseline(g, X, Q, mode, ef, k, rerank, budget_s=20.0, single_s=10.0):
     dt1 = time.perf_counter() - t
     single = {"value": n1 / dt1, "unit": "queries/s", "threads": 1,
               "sample": f"first {n1} queries, {dt1:.1f}s"}
-    return out, single
+    # EXACT keys: whole rounds of one query per thread until the budget is spent
+    ne, t = 0, time.perf_counter()
+    while ne < Q.shape[0] and (ne == 0 or time.perf_counter() - t < exact_s):
+        b = min(probe, Q.shape[0] - ne)
+        oracle.hnsw_search(g, st, k, ef, Q=Q[ne:ne + b], kmode="exact",
+                           rerank_f32=X if rerank else None, rerank=rerank,
+                           rerank_kmode="exact", threads=threads)
+        ne += b
+    dte = time.perf_counter() - t
+    exact = {"value": ne / dte, "unit": "queries/s", "threads": threads,
+             "sample": f"first {ne} queries, EXACT keys and rerank, {dte:.1f}s"}
+    return out, single, exact
 
 
 def main():
@@ -854,11 +866,11 @@ def main():
         except ann.AnnError as e:
             log(f"serving skipped: {e}")
 
-    cpu = cpu1 = None
+    cpu = cpu1 = cpux = None
     if not a.no_cpu:
-        cpu, cpu1 = cpu_baseline(g, X, Q, a.mode, ef, k, a.rerank)
+        cpu, cpu1, cpux = cpu_baseline(g, X, Q, a.mode, ef, k, a.rerank)
         log(f"cpu oracle: {cpu['value']:.1f} QPS on {cpu['cores']} threads, "
-            f"{cpu1['value']:.2f} QPS on one thread")
+            f"{cpu1['value']:.2f} QPS on one thread, {cpux['value']:.1f} QPS with EXACT keys")
 
     traffic = None
     tp = os.path.join(PROFILES, f"search_{a.workload}_traffic.json")
@@ -906,6 +918,7 @@ def main():
                     "serving": serve32, "launch": launch32},
             "bf16+rerank": bf16_row,
             "cpu_oracle_single_thread": cpu1,
+            "cpu_oracle_exact_keys": cpux,
             "wall_s": round(wall, 3),
             "bruteforce_mfma": bf,
             "ivf": ivf_rows,
