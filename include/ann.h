@@ -390,15 +390,23 @@ int ann_plan_free(ann_plan* plan);
 
 /*
  * Exact k-NN by a full scan (the k-nearest-neighbour problem of Section 1),
- * for ground truth.  Matrix-core (MFMA, FP32) tiles of Q x X^T preselect 64
- * candidates per query and row range; the best k + 16 are then re-scored
- * with the FP32 rows in the fixed FP32 order above and sorted by (key, id).
+ * for ground truth.  Matrix-core tiles of Q x X^T preselect 64 candidates per
+ * query and row range; the best k + 16 are then re-scored with the FP32 rows
+ * in the fixed FP32 order above and sorted by (key, id).  The preselection
+ * runs first on FP16 copies of the rows and queries (v_mfma_f32_16x16x32_f16;
+ * the rows' copy, 2 n d bytes, is made on the first call and kept by the
+ * index) when d is a multiple of 8 and every row value is inside the FP16
+ * range; queries whose result that pass cannot certify are scanned again
+ * with FP32 tiles (v_mfma_f32_16x16x4_f32), which is also the only pass
+ * otherwise.  Either way a certified result is the exact top-k.
  *   queries        device f32[nq][d]
  *   out_ids        device i64[nq][k], out_dists device f32[nq][k]
- *   out_certified  optional device i32[nq]: 1 when the result is provably
- *                  the exact top-k under the fixed-order keys (the gap to
- *                  every candidate not re-scored exceeds the worst-case
- *                  difference between the MFMA and fixed-order sums), else 0
+ *   out_certified  optional device i32[nq]: nonzero when the result is
+ *                  provably the exact top-k under the fixed-order keys (the
+ *                  gap to every candidate not re-scored exceeds the worst-
+ *                  case difference between the preselection's and the
+ *                  fixed-order keys): 2 when the FP16 pass certified it, 1
+ *                  when the FP32 pass did; else 0
  * 1 <= k <= 48.  Needs x_f32.  Asynchronous on `stream` (NULL: the index
  * stream, blocking).  Uses a scratch buffer the index keeps (grown on
  * demand): the kernels of calls on one index run one call after the other
@@ -411,8 +419,10 @@ int ann_bruteforce(const ann_index* ix, const float* queries, int64_t nq, int32_
 /*
  * ann_bruteforce with no device allocation, for callers that cannot
  * allocate memory: code under HIP graph capture, tight serving loops,
- * harnesses that forbid hipMalloc.  Same arguments, results and errors as
- * ann_bruteforce, bit for bit.  Its scratch (the row norms and the candidate
+ * harnesses that forbid hipMalloc.  Same arguments and errors as
+ * ann_bruteforce, and the same ids and keys, bit for bit, for every query
+ * that both certify; it runs the FP32 tiles only (out_certified 0 or 1),
+ * since the rows' FP16 copy would be an allocation.  Its scratch (the row norms and the candidate
  * lists: 4 n + 512 nq r bytes, each rounded up to 256, where r is the
  * number of row ranges the scan splits the rows into, at most 32) lives in
  * a fixed device array of ANN_NOALLOC_SCRATCH_BYTES that each GPU the

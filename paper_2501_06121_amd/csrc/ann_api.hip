@@ -478,6 +478,7 @@ int ann_index_free(ann_index* ix) {
   hipDeviceSynchronize();
   ix->ws.release();
   if (ix->bf_scratch) (void)hipFree(ix->bf_scratch);
+  if (ix->bf_xh) (void)hipFree(ix->bf_xh);
   if (ix->bf_done) (void)hipEventDestroy(ix->bf_done);
   void* ptrs[] = {ix->adj0, ix->upper_off, ix->upper_adj, ix->x_f32, ix->x_f16, ix->x_bf16,
                   ix->x_fp8, ix->fp8_scale, ix->pq_cb, ix->pq_codes, ix->sp_ptr, ix->sp_ids,

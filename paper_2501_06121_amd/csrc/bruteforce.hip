@@ -22,6 +22,14 @@
 //   k-th exact key plus the worst-case difference between the MFMA and the
 //   fixed-order evaluations stays below the approximate key of every
 //   candidate that was not re-scored.
+//
+// Half-precision preselection (bf_tiles_h): the same scan with FP16 copies
+// of the rows and queries (rounded to nearest even from the FP32 values) on
+// v_mfma_f32_16x16x32_f16, eight times the FP32 matrix rate and half the
+// bytes per row.  Its certificate adds the rounding of the operands to the
+// bound.  Queries it cannot certify are scanned again by the FP32 tiles
+// (whose workgroups skip query blocks with nothing to redo), so the call
+// returns the same exact top-k either way.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -146,7 +154,20 @@ struct BfParams {
   int admit;             // a row enters a list when it beats the list's admit-th entry
   float* cand_key;       // [nq][nranges][KC]
   int32_t* cand_id;
+  const int32_t* redo;   // optional [nq]: only blocks with a query whose flag is 0 are scanned
+  const uint16_t* Xh;    // FP16 copies (bf_tiles_h): rows [n][d], queries [nq][d]
+  const uint16_t* Qh;
 };
+
+// Whether this workgroup's block of BM queries has work: without a redo mask
+// always; with one, when some query of the block was not certified.
+__device__ __forceinline__ bool block_has_work(const BfParams& p, int64_t q0) {
+  if (!p.redo) return true;
+  const int tid = threadIdx.x;
+  const int64_t q = q0 + tid;
+  const int need = (tid < BM && q < p.nq && p.redo[q] == 0) ? 1 : 0;
+  return __syncthreads_or(need) != 0;
+}
 
 // One stage (32 dimensions from k0) of the query block and of a base tile:
 // 4 float4 of each per thread, zero outside the matrices.
@@ -188,6 +209,87 @@ __device__ __forceinline__ void store_stage(float* sa, float* sb, const StageReg
   }
 }
 
+// The 128 x 128 block of a tile (accumulators of the four waves: row
+// wq + 16 rb + 4 (lane / 16) + r, column wx + 16 cb + lane % 16) as
+// approximate keys in the LDS tile.
+__device__ __forceinline__ void tile_keys(const BfParams& p, const floatx4 (&acc)[4][4], float* tile,
+                                          int64_t t0, int64_t r_end, int wq, int wx, int lane) {
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      const int col = wx + cb * 16 + (lane & 15);
+      const int64_t xi = t0 + col;
+      const float x2 = (p.metric == METRIC_IP || xi >= r_end) ? 0.0f : p.x2[xi];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = wq + rb * 16 + 4 * (lane >> 4) + r;
+        const float dot = acc[rb][cb][r];
+        float key = __builtin_inff();
+        if (xi < r_end) key = (p.metric == METRIC_IP) ? -dot : x2 - 2.0f * dot;
+        tile[row * TLD + col] = key;
+      }
+    }
+}
+
+// Merge the key tile into the per-query lists (each wave its 32 queries).
+__device__ __forceinline__ void tile_merge(const BfParams& p, const float* tile, float (*lk)[KC],
+                                           int (*li)[KC], int64_t q0, int64_t t0, int64_t r_end,
+                                           int wave, int lane) {
+  // each wave merges its 32 queries, 64 columns at a time.  First every
+  // lane screens one (query, half tile) against that query's admission
+  // entry; only the flagged pairs take the wave-wide path (a later merge
+  // only lowers the entry, so an unflagged pair stays out)
+  static_assert(BN == 128 && BM / 4 == 32, "one lane per (query, half tile) of the wave");
+  bool hit = false;
+  {
+    const int row = wave * (BM / 4) + (lane >> 1);
+    const int c0 = (lane & 1) * 64;
+    if (q0 + row < p.nq) {
+      const float thr_k = lk[row][p.admit - 1];
+      const int thr_i = li[row][p.admit - 1];
+      for (int c = 0; c < 64; ++c) {
+        const int col = c0 + c;
+        const int id = (t0 + col < r_end) ? (int)(t0 + col) : 0x7FFFFFFF;
+        hit = hit | kid_less(tile[row * TLD + col], id, thr_k, thr_i);
+      }
+    }
+  }
+  for (uint64_t todo = __ballot(hit); todo; todo &= todo - 1) {
+    const int j = __builtin_ctzll(todo);
+    const int row = wave * (BM / 4) + (j >> 1);
+    const int col = (j & 1) * 64 + lane;
+    const float thr_k = lk[row][p.admit - 1];
+    const int thr_i = li[row][p.admit - 1];
+    float k = tile[row * TLD + col];
+    // columns past the range are empty entries (+inf, largest id)
+    int id = (t0 + col < r_end) ? (int)(t0 + col) : 0x7FFFFFFF;
+    const bool keep = kid_less(k, id, thr_k, thr_i);
+    const uint64_t km = __ballot(keep);
+    if (!km) continue;
+    if (__builtin_popcountll(km) > 8) {
+      if (!keep) { k = __builtin_inff(); id = 0x7FFFFFFF; }
+      merge_list(lk[row], li[row], k, id);
+    } else {
+      insert_few(lk[row], li[row], k, id, km);
+    }
+  }
+}
+
+// The lists of a workgroup's queries out to the candidate arrays.
+__device__ __forceinline__ void lists_out(const BfParams& p, float (*lk)[KC], int (*li)[KC], int64_t q0,
+                                          int range) {
+  for (int i = threadIdx.x; i < BM * KC; i += blockDim.x) {
+    const int r = i / KC, c = i % KC;
+    const int64_t qi = q0 + r;
+    if (qi < p.nq) {
+      const size_t o = ((size_t)qi * p.nranges + range) * KC + c;
+      p.cand_key[o] = lk[r][c];
+      p.cand_id[o] = li[r][c];
+    }
+  }
+}
+
 __global__ void __launch_bounds__(256) bf_tiles(BfParams p) {
   __shared__ float stage[kStageFloats];   // [2][BK][LDA] queries, [2][BK][LDB] rows; later the key tile
   __shared__ float lk[BM][KC];
@@ -206,6 +308,7 @@ __global__ void __launch_bounds__(256) bf_tiles(BfParams p) {
   float* const sb = stage + 2 * BK * LDA;   // of the rows: sb + b * BK * LDB
   float* const tile = stage;
   const int nst = (p.d + BK - 1) / BK;
+  if (!block_has_work(p, q0)) return;
 
   for (int i = tid; i < BM * KC; i += 256) {
     lk[i / KC][i % KC] = __builtin_inff();
@@ -245,75 +348,139 @@ __global__ void __launch_bounds__(256) bf_tiles(BfParams p) {
       if (s + 1 < nst) store_stage(sa + (buf ^ 1) * (BK * LDA), sb + (buf ^ 1) * (BK * LDB), regs);
       __syncthreads();
     }
-    // approximate keys into the tile: row wq + 16 rb + 4 (lane / 16) + r, col wx + 16 cb + lane % 16
-#pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-      for (int cb = 0; cb < 4; ++cb) {
-        const int col = wx + cb * 16 + (lane & 15);
-        const int64_t xi = t0 + col;
-        const float x2 = (p.metric == METRIC_IP || xi >= r_end) ? 0.0f : p.x2[xi];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = wq + rb * 16 + 4 * (lane >> 4) + r;
-          const float dot = acc[rb][cb][r];
-          float key = __builtin_inff();
-          if (xi < r_end) key = (p.metric == METRIC_IP) ? -dot : x2 - 2.0f * dot;
-          tile[row * TLD + col] = key;
-        }
-      }
+    tile_keys(p, acc, tile, t0, r_end, wq, wx, lane);
     __syncthreads();
     // the next tile's first stage is in flight while the lists are merged
     if (t0 + BN < r_end) load_stage(p, q0, t0 + BN, r_end, 0, regs);
-    // each wave merges its 32 queries, 64 columns at a time.  First every
-    // lane screens one (query, half tile) against that query's admission
-    // entry; only the flagged pairs take the wave-wide path (a later merge
-    // only lowers the entry, so an unflagged pair stays out)
-    static_assert(BN == 128 && BM / 4 == 32, "one lane per (query, half tile) of the wave");
-    bool hit = false;
-    {
-      const int row = wave * (BM / 4) + (lane >> 1);
-      const int c0 = (lane & 1) * 64;
-      if (q0 + row < p.nq) {
-        const float thr_k = lk[row][p.admit - 1];
-        const int thr_i = li[row][p.admit - 1];
-        for (int c = 0; c < 64; ++c) {
-          const int col = c0 + c;
-          const int id = (t0 + col < r_end) ? (int)(t0 + col) : 0x7FFFFFFF;
-          hit = hit | kid_less(tile[row * TLD + col], id, thr_k, thr_i);
-        }
-      }
-    }
-    for (uint64_t todo = __ballot(hit); todo; todo &= todo - 1) {
-      const int j = __builtin_ctzll(todo);
-      const int row = wave * (BM / 4) + (j >> 1);
-      const int col = (j & 1) * 64 + lane;
-      const float thr_k = lk[row][p.admit - 1];
-      const int thr_i = li[row][p.admit - 1];
-      float k = tile[row * TLD + col];
-      // columns past the range are empty entries (+inf, largest id)
-      int id = (t0 + col < r_end) ? (int)(t0 + col) : 0x7FFFFFFF;
-      const bool keep = kid_less(k, id, thr_k, thr_i);
-      const uint64_t km = __ballot(keep);
-      if (!km) continue;
-      if (__builtin_popcountll(km) > 8) {
-        if (!keep) { k = __builtin_inff(); id = 0x7FFFFFFF; }
-        merge_list(lk[row], li[row], k, id);
-      } else {
-        insert_few(lk[row], li[row], k, id, km);
-      }
-    }
+    tile_merge(p, tile, lk, li, q0, t0, r_end, wave, lane);
   }
   __syncthreads();
-  for (int i = tid; i < BM * KC; i += 256) {
-    const int r = i / KC, c = i % KC;
-    const int64_t qi = q0 + r;
-    if (qi < p.nq) {
-      const size_t o = ((size_t)qi * p.nranges + range) * KC + c;
-      p.cand_key[o] = lk[r][c];
-      p.cand_id[o] = li[r][c];
-    }
+  lists_out(p, lk, li, q0, range);
+}
+
+// ---- half-precision preselection ---------------------------------------
+
+constexpr int BKH = 64;         // dimensions per stage
+constexpr int LDH = BKH + 8;    // row stride in halves: 144 B, so 16 rows of a 16-byte
+                                // read start on 16 different 4-bank groups
+static_assert(2 * 2 * BM * LDH * 2 <= kStageFloats * 4, "two half stages fit the stage buffers");
+
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+
+// FP16 copy, rounded to nearest even; values beyond the FP16 range saturate
+// (the finishing kernel refuses to certify a query that needed it).
+__global__ void bf_half(const float* src, int64_t count, uint16_t* dst) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float v = fminf(fmaxf(src[i], -65504.0f), 65504.0f);
+    dst[i] = __builtin_bit_cast(uint16_t, (_Float16)v);
   }
+}
+
+// One stage (64 dimensions from k0) of the query block and a base tile: 256
+// rows (queries first) of 8 16-byte chunks, 8 chunks per thread, zero outside
+// the matrices (d is a multiple of 8: a chunk is wholly in or out).
+struct StageRegsH {
+  uint4 v[8];
+};
+
+__device__ __forceinline__ void load_stage_h(const BfParams& p, int64_t q0, int64_t t0,
+                                             int64_t r_end, int k0, StageRegsH& r) {
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int idx = threadIdx.x + 256 * u;
+    const int row = idx >> 3;
+    const int k = k0 + 8 * (idx & 7);
+    const uint16_t* src = nullptr;
+    if (row < BM) {
+      const int64_t qi = q0 + row;
+      if (qi < p.nq && k < p.d) src = p.Qh + qi * p.d + k;
+    } else {
+      const int64_t xi = t0 + (row - BM);
+      if (xi < r_end && k < p.d) src = p.Xh + xi * p.d + k;
+    }
+    r.v[u] = src ? *(const uint4*)src : make_uint4(0u, 0u, 0u, 0u);
+  }
+}
+
+__device__ __forceinline__ void store_stage_h(uint16_t* sbuf, const StageRegsH& r) {
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int idx = threadIdx.x + 256 * u;
+    *(uint4*)(sbuf + (idx >> 3) * LDH + 8 * (idx & 7)) = r.v[u];
+  }
+}
+
+// bf_tiles with FP16 operands on v_mfma_f32_16x16x32_f16: the same blocks,
+// lists, admission and output, 64 dimensions per stage.
+__global__ void __launch_bounds__(256) bf_tiles_h(BfParams p) {
+  __shared__ float stage[kStageFloats];   // [2][256 rows][LDH] halves; later the key tile
+  __shared__ float lk[BM][KC];
+  __shared__ int li[BM][KC];
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int wq = (wave & 1) * 64;
+  const int wx = (wave >> 1) * 64;
+  const int64_t q0 = (int64_t)blockIdx.x * BM;
+  const int range = blockIdx.y;
+  const int64_t r_begin = (int64_t)range * p.rows_per_range;
+  const int64_t r_end = r_begin + p.rows_per_range < p.n ? r_begin + p.rows_per_range : p.n;
+  uint16_t* const sh = (uint16_t*)stage;   // stage buffer b: sh + b * 2 * BM * LDH
+  float* const tile = stage;
+  const int nst = (p.d + BKH - 1) / BKH;
+  if (!block_has_work(p, q0)) return;
+
+  for (int i = tid; i < BM * KC; i += 256) {
+    lk[i / KC][i % KC] = __builtin_inff();
+    li[i / KC][i % KC] = 0x7FFFFFFF;
+  }
+
+  StageRegsH regs;
+  if (r_begin < r_end) load_stage_h(p, q0, r_begin, r_end, 0, regs);
+  for (int64_t t0 = r_begin; t0 < r_end; t0 += BN) {
+    __syncthreads();                      // the previous tile's keys have been read
+    store_stage_h(sh, regs);
+    __syncthreads();
+    floatx4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int st = 0; st < nst; ++st) {
+      const int buf = st & 1;
+      if (st + 1 < nst) load_stage_h(p, q0, t0, r_end, (st + 1) * BKH, regs);
+      const uint16_t* S = sh + buf * (2 * BM * LDH);
+#pragma unroll
+      for (int j = 0; j < BKH / 32; ++j) {
+        // lane: row lane % 16 of each 16-row block, dimensions 8 (lane / 16) ..
+        // of this 32-dimension step; queries and rows take the same
+        // dimensions, so each product sums over all 32 of them
+        const int ko = 32 * j + 8 * (lane >> 4);
+        halfx8 av[4], bv[4];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+          av[rb] = *(const halfx8*)(S + (wq + rb * 16 + (lane & 15)) * LDH + ko);
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+          bv[cb] = *(const halfx8*)(S + (BM + wx + cb * 16 + (lane & 15)) * LDH + ko);
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb)
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[rb], bv[cb], acc[rb][cb], 0, 0, 0);
+      }
+      if (st + 1 < nst) store_stage_h(sh + (buf ^ 1) * (2 * BM * LDH), regs);
+      __syncthreads();
+    }
+    tile_keys(p, acc, tile, t0, r_end, wq, wx, lane);
+    __syncthreads();
+    if (t0 + BN < r_end) load_stage_h(p, q0, t0 + BN, r_end, 0, regs);
+    tile_merge(p, tile, lk, li, q0, t0, r_end, wave, lane);
+  }
+  __syncthreads();
+  lists_out(p, lk, li, q0, range);
 }
 
 struct BfFinish {
@@ -328,6 +495,8 @@ struct BfFinish {
   const int32_t* cand_id;
   int k;
   float xmax, x2max;
+  int half;              // the candidates come from bf_tiles_h: its operand rounding joins the bound
+  const int32_t* redo;   // optional [nq]: queries flagged 1 are done (certified by the half pass)
   int64_t* out_ids;
   float* out_dists;
   int32_t* out_certified;
@@ -340,6 +509,10 @@ __global__ void __launch_bounds__(64) bf_finish(BfFinish p) {
   const int lane = threadIdx.x;
   const int64_t q = blockIdx.x;
   if (q >= p.nq) return;
+  if (p.redo && p.redo[q]) {
+    if (lane == 0 && p.out_certified) p.out_certified[q] = 2;   // certified by the half pass
+    return;
+  }
   lk[lane] = __builtin_inff();
   li[lane] = 0x7FFFFFFF;
   __syncthreads();
@@ -349,9 +522,17 @@ __global__ void __launch_bounds__(64) bf_finish(BfFinish p) {
   }
   const float* qr = p.Q + q * p.d;
   // |q|_1 and |q|^2 for the error bound and the L2 offset
-  float a1 = 0.f, q2 = 0.f;
-  for (int i = lane; i < p.d; i += 64) { a1 += fabsf(qr[i]); q2 = __builtin_fmaf(qr[i], qr[i], q2); }
-  for (int s = 32; s >= 1; s >>= 1) { a1 += __shfl_xor(a1, s, 64); q2 += __shfl_xor(q2, s, 64); }
+  float a1 = 0.f, q2 = 0.f, qm = 0.f;
+  for (int i = lane; i < p.d; i += 64) {
+    a1 += fabsf(qr[i]);
+    q2 = __builtin_fmaf(qr[i], qr[i], q2);
+    qm = fmaxf(qm, fabsf(qr[i]));
+  }
+  for (int s = 32; s >= 1; s >>= 1) {
+    a1 += __shfl_xor(a1, s, 64);
+    q2 += __shfl_xor(q2, s, 64);
+    qm = fmaxf(qm, __shfl_xor(qm, s, 64));
+  }
   // exact re-score of the best R candidates: 64 lanes per row, the fixed
   // FP32 order (chunk g of 4 floats feeds partial g mod 64 = lane)
   const int R = p.k + kRescore < KC ? p.k + kRescore : KC;
@@ -402,15 +583,33 @@ __global__ void __launch_bounds__(64) bf_finish(BfFinish p) {
   // and the fixed-order keys differ by at most E
   const float u = 0x1p-24f;
   float E = 2.0f * (float)(p.d + 16) * u;
-  E *= (p.metric == METRIC_IP) ? a1 * p.xmax : 2.0f * a1 * p.xmax + p.x2max + q2;
+  if (!p.half) {
+    E *= (p.metric == METRIC_IP) ? a1 * p.xmax : 2.0f * a1 * p.xmax + p.x2max + q2;
+  } else {
+    // S bounds sum |q_i x_i| for every row: by |q|_1 max|x_ij| or by Cauchy-
+    // Schwarz (|q|_2 max |x|_2), with 0.1% for the rounding of a1, q2, x2max
+    const float S = fminf(a1 * p.xmax, sqrtf(q2) * sqrtf(p.x2max)) * 1.001f;
+    E *= (p.metric == METRIC_IP) ? S : 2.0f * S + p.x2max + q2;
+    // FP16 operands: each factor within a relative 2^-11 (round to nearest
+    // even) or an absolute 2^-25 (subnormals) of its FP32 value; the product
+    // of two such within (2^-10 + 2^-22) |q_i x_i| + 2^-25 (1 + 2^-11)(|q_i| + |x_i|) + 2^-50
+    const float eh = (0x1p-10f + 0x1p-22f) * S +
+                     0x1p-25f * (1.0f + 0x1p-11f) * (a1 + (float)p.d * p.xmax) + (float)p.d * 0x1p-50f;
+    E = (E * (1.0f + 0x1p-9f) + ((p.metric == METRIC_IP) ? eh : 2.0f * eh)) * (1.0f + 0x1p-16f);
+  }
   float kth = __shfl(kx, 0, 64);
   for (int j = 0; j < 64; ++j) {
     const int rj = __shfl(rank, j, 64);
     if (rj == p.k - 1) kth = __shfl(kx, j, 64);
   }
-  float thr = (R < KC) ? lk[R] : __builtin_inff();
+  // every candidate not re-scored sorts after lk[R] (R < KC), and every row
+  // outside the merged list after lk[KC - 1] (each range's list holds its
+  // best KC, and the merged list the best KC of those)
+  float thr = (R < KC) ? lk[R] : lk[KC - 1];
   if (p.metric != METRIC_IP) thr += q2;
-  if (lane == 0 && p.out_certified) p.out_certified[q] = (R >= KC) || (kth + E < thr) ? 1 : 0;
+  // a query beyond the FP16 range was saturated: no bound holds for it
+  const bool in_range = !p.half || qm <= 65504.0f;
+  if (lane == 0 && p.out_certified) p.out_certified[q] = in_range && (kth + E < thr) ? 1 : 0;
 }
 
 }  // namespace
@@ -456,9 +655,13 @@ int bf_check(const ann_index* ix, const float* queries, int64_t nq, int32_t k, c
 
 // The three kernels of one call, with the row norms (x2, written first when
 // norms is set) and the candidate lists (ckey, cid) at the given addresses.
+// With xh (the rows' FP16 copy), qh and hcert (scratch for the queries' FP16
+// copy and the half pass's certificates), the half-precision pass runs first
+// and the FP32 tiles redo only the queries it could not certify.
 int bf_launch(const ann_index* ix, const float* queries, int64_t nq, int32_t k, int64_t* out_ids,
               float* out_dists, int32_t* out_certified, hipStream_t st, int nranges, float* x2,
-              float* ckey, int32_t* cid, bool norms) {
+              float* ckey, int32_t* cid, bool norms, const uint16_t* xh = nullptr,
+              uint16_t* qh = nullptr, int32_t* hcert = nullptr) {
   if (norms) {
     hipLaunchKernelGGL(bf_norms, dim3((unsigned)ix->n), dim3(64), 0, st, ix->x_f32, ix->n, ix->d, x2);
     HIP_OR_RETURN(hipGetLastError(), "bf_norms launch");
@@ -473,17 +676,59 @@ int bf_launch(const ann_index* ix, const float* queries, int64_t nq, int32_t k, 
   // are not inserted (entries further down may then be stale).
   p.admit = std::min(KC, k + kRescore + 1);
   p.cand_key = ckey; p.cand_id = cid;
+  p.redo = nullptr; p.Xh = nullptr; p.Qh = nullptr;
   const dim3 grid((unsigned)((nq + BM - 1) / BM), (unsigned)nranges);
-  hipLaunchKernelGGL(bf_tiles, grid, dim3(256), 0, st, p);
-  HIP_OR_RETURN(hipGetLastError(), "bf_tiles launch");
   BfFinish f;
   f.X = ix->x_f32; f.n = ix->n; f.d = ix->d; f.metric = ix->metric; f.Q = queries; f.nq = nq;
   f.nranges = nranges; f.cand_key = ckey; f.cand_id = cid; f.k = k;
   f.xmax = ix->xmax; f.x2max = ix->x2max;
-  f.out_ids = out_ids; f.out_dists = out_dists; f.out_certified = out_certified;
+  f.out_ids = out_ids; f.out_dists = out_dists;
+  if (xh) {
+    const int64_t cnt = nq * ix->d;
+    hipLaunchKernelGGL(bf_half, dim3((unsigned)std::min<int64_t>((cnt + 255) / 256, 16384)), dim3(256), 0,
+                       st, queries, cnt, qh);
+    HIP_OR_RETURN(hipGetLastError(), "bf_half launch");
+    p.Xh = xh; p.Qh = qh;
+    hipLaunchKernelGGL(bf_tiles_h, grid, dim3(256), 0, st, p);
+    HIP_OR_RETURN(hipGetLastError(), "bf_tiles_h launch");
+    f.half = 1; f.redo = nullptr; f.out_certified = hcert;
+    hipLaunchKernelGGL(bf_finish, dim3((unsigned)nq), dim3(64), 0, st, f);
+    HIP_OR_RETURN(hipGetLastError(), "bf_finish launch");
+    p.redo = hcert;
+    f.redo = hcert;
+  } else {
+    f.redo = nullptr;
+  }
+  hipLaunchKernelGGL(bf_tiles, grid, dim3(256), 0, st, p);
+  HIP_OR_RETURN(hipGetLastError(), "bf_tiles launch");
+  f.half = 0; f.out_certified = out_certified;
   hipLaunchKernelGGL(bf_finish, dim3((unsigned)nq), dim3(64), 0, st, f);
   HIP_OR_RETURN(hipGetLastError(), "bf_finish launch");
   return ANN_OK;
+}
+
+// The rows' FP16 copy for the half-precision pass, made once per index; null
+// (FP32 tiles only) when the rows do not suit it (d not a multiple of 8,
+// values beyond the FP16 range) or the memory is not there.
+const uint16_t* half_rows(ann_index* ix, hipStream_t st) {
+  if (ix->d % 8 != 0 || !(ix->xmax < 65504.0f)) return nullptr;
+  if (!ix->bf_xh) {
+    const size_t bytes = (size_t)ix->n * ix->d * 2;
+    if (hipMalloc(&ix->bf_xh, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      ix->bf_xh = nullptr;
+      return nullptr;
+    }
+    const int64_t cnt = ix->n * ix->d;
+    hipLaunchKernelGGL(bf_half, dim3((unsigned)std::min<int64_t>((cnt + 255) / 256, 16384)), dim3(256), 0,
+                       st, ix->x_f32, cnt, (uint16_t*)ix->bf_xh);
+    if (hipGetLastError() != hipSuccess) {
+      (void)hipFree(ix->bf_xh);
+      ix->bf_xh = nullptr;
+      return nullptr;
+    }
+  }
+  return (const uint16_t*)ix->bf_xh;
 }
 
 }  // namespace
@@ -499,7 +744,9 @@ extern "C" int ann_bruteforce(const ann_index* cix, const float* queries, int64_
   HIP_OR_RETURN(hipSetDevice(ix->device), "hipSetDevice");
   hipStream_t st = stream ? (hipStream_t)stream : ix->stream;
   const int nranges = bf_ranges(ix->n, nq, ix->cu_count > 0 ? ix->cu_count : 256);
-  const size_t need = bruteforce_scratch_bytes(ix->n, nq, nranges);
+  // the half pass's extra scratch: the queries' FP16 copy and its certificates
+  const size_t half_extra = (((size_t)nq * ix->d * 2 + 255) & ~size_t(255)) + (size_t)nq * 4;
+  const size_t need = bruteforce_scratch_bytes(ix->n, nq, nranges) + half_extra;
   if (!ix->bf_done)
     HIP_OR_RETURN(hipEventCreateWithFlags(&ix->bf_done, hipEventDisableTiming), "hipEventCreate");
   if (ix->bf_scratch_bytes < need) {
@@ -521,8 +768,11 @@ extern "C" int ann_bruteforce(const ann_index* cix, const float* queries, int64_
   float* x2 = (float*)base;
   float* ckey = (float*)(base + (((size_t)ix->n * 4 + 255) & ~size_t(255)));
   int32_t* cid = (int32_t*)(ckey + (size_t)nq * nranges * KC);
+  uint16_t* qh = (uint16_t*)(base + bruteforce_scratch_bytes(ix->n, nq, nranges));
+  int32_t* hcert = (int32_t*)((char*)qh + (((size_t)nq * ix->d * 2 + 255) & ~size_t(255)));
+  const uint16_t* xh = half_rows(ix, st);
   rc = bf_launch(ix, queries, nq, k, out_ids, out_dists, out_certified, st, nranges, x2, ckey, cid,
-                 !ix->bf_norms_ready);
+                 !ix->bf_norms_ready, xh, xh ? qh : nullptr, xh ? hcert : nullptr);
   if (rc) return rc;
   ix->bf_norms_ready = true;
   HIP_OR_RETURN(hipEventRecord(ix->bf_done, st), "hipEventRecord");

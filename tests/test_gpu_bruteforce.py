@@ -36,6 +36,42 @@ def test_bruteforce_ip_768(vmf_small):
     check(vmf_small["X"], vmf_small["Q"], "ip", 10, vmf_small["graph"])
 
 
+def test_half_pass_and_fp32_redo():
+    """The FP16 preselection certifies what its wider bound allows (flag 2);
+    the rest is redone by the FP32 tiles (flag 1).  Rows and queries near
+    (1, ..., 1) have keys within a few hundredths of each other: the FP16
+    bound (about 2^-10 of |q| |x| = 64) cannot separate them and the FP32
+    one (about 1e-3) can, so nearly every query goes through the redo; on
+    the Gaussian mixture the FP16 pass certifies them itself."""
+    rng = np.random.default_rng(11)
+    X = (1.0 + 0.01 * rng.standard_normal((3000, 64))).astype(np.float32)
+    Q = (1.0 + 0.01 * rng.standard_normal((200, 64))).astype(np.float32)
+    g = oracle.hnsw_build(X, "ip", 8, 32, np.zeros(X.shape[0]))
+    ix = ann.ann_index_create(g, "ip", 64, x_f32=X)
+    try:
+        ids, d, cert = ann.ann_bruteforce(ix, torch.from_numpy(Q).to("cuda:0"), 10)
+        torch.cuda.synchronize()
+        ids, d, cert = ids.cpu().numpy(), d.cpu().numpy(), cert.cpu().numpy()
+    finally:
+        ix.close()
+    ref_ids, ref_k = oracle.bruteforce(oracle.dense_store(X, "ip"), X.shape[0], 10, Q=Q,
+                                       kmode="canon")
+    assert np.array_equal(ids, ref_ids) and np.array_equal(d, ref_k)
+    assert np.all(cert != 0) and np.mean(cert == 1) > 0.9, np.bincount(cert)
+
+
+def test_half_pass_certifies_the_mixture(gmm10k):
+    X, Q, g = gmm10k["X"], gmm10k["Q"], gmm10k["graph"]
+    ix = ann.ann_index_create(g, "l2", X.shape[1], x_f32=X)
+    try:
+        ids, d, cert = ann.ann_bruteforce(ix, torch.from_numpy(Q).to("cuda:0"), 10)
+        torch.cuda.synchronize()
+        cert = cert.cpu().numpy()
+    finally:
+        ix.close()
+    assert np.all(cert != 0) and np.mean(cert == 2) > 0.9, np.bincount(cert)
+
+
 def test_bruteforce_ragged_and_tiny():
     # n not a multiple of the 128-row tile, nq not a multiple of 128, n < k
     rng = np.random.default_rng(3)

@@ -50,9 +50,10 @@ def test_noalloc_equals_bruteforce_on_two_calls(gmm10k, metric):
             say(f"{metric}: {Q.shape[0]} queries, k={k}")
             a = call("ann_bruteforce_noalloc", ix, Q, k)
             b = call("ann_bruteforce", ix, Q, k)
-            for x, y in zip(a, b):
-                assert np.array_equal(x, y)
-            assert a[2].all()
+            # ids and keys bit for bit; ann_bruteforce may certify by its
+            # FP16 pass (2), the variant without allocation by FP32 tiles (1)
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+            assert np.all(a[2] == 1) and np.all(b[2] != 0)
     finally:
         ix.close()
     # and the oracle's exact scan agrees
