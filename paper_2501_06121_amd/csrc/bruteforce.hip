@@ -34,6 +34,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "ann.h"
 #include "internal.h"
@@ -49,9 +50,9 @@ constexpr int KC = 64;      // candidates kept per query and range
 constexpr int kRescore = 16;
 constexpr int LDA = BM + 16;   // k-major stage rows (16 mod 32 banks: conflict-free reads)
 constexpr int LDB = BN + 16;
-constexpr int TLD = BN + 1;    // key tile row length
+constexpr int TLT = BM + 4;    // key tile column length (a multiple of 4: 16-byte stores)
 constexpr int kStageFloats = 2 * BK * (LDA + LDB);
-static_assert(BM * TLD <= kStageFloats, "the key tile reuses the stage buffers");
+static_assert(BN * TLT <= kStageFloats, "the key tile reuses the stage buffers");
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
@@ -170,7 +171,12 @@ __device__ __forceinline__ bool block_has_work(const BfParams& p, int64_t q0) {
 }
 
 // One stage (32 dimensions from k0) of the query block and of a base tile:
-// 4 float4 of each per thread, zero outside the matrices.
+// 4 float4 of each per thread.  The loads are unconditional (rows past the
+// matrices read their last row, dimensions past d read dimension 0): a load
+// under a per-lane condition makes the compiler wait for it on the spot,
+// which would serialise the prefetch.  Rows past the matrices are never
+// used (their keys are +inf, their lists are not written); dimensions past
+// d are zeroed when the stage is stored.
 struct StageRegs {
   float4 q[4];
   float4 x[4];
@@ -183,85 +189,97 @@ __device__ __forceinline__ void load_stage(const BfParams& p, int64_t q0, int64_
   for (int u = 0; u < 4; ++u) {
     const int idx = tid + 256 * u;       // 1024 float4 per operand: row idx / 8, float4 idx % 8
     const int row = idx >> 3;
-    const int k = k0 + 4 * (idx & 7);
-    const int64_t qi = q0 + row;
-    const int64_t xi = t0 + row;
-    r.q[u] = (qi < p.nq && k < p.d) ? *(const float4*)(p.Q + qi * p.d + k) : make_float4(0.f, 0.f, 0.f, 0.f);
-    r.x[u] = (xi < r_end && k < p.d) ? *(const float4*)(p.X + xi * p.d + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+    int k = k0 + 4 * (idx & 7);
+    k = k < p.d ? k : 0;
+    const int64_t qi = q0 + row < p.nq ? q0 + row : p.nq - 1;
+    const int64_t xi = t0 + row < r_end ? t0 + row : r_end - 1;
+    r.q[u] = *(const float4*)(p.Q + qi * p.d + k);
+    r.x[u] = *(const float4*)(p.X + xi * p.d + k);
   }
 }
 
-__device__ __forceinline__ void store_stage(float* sa, float* sb, const StageRegs& r) {
+__device__ __forceinline__ void store_stage(float* sa, float* sb, const StageRegs& r, int k0, int d) {
   const int tid = threadIdx.x;
+  // the thread's dimensions are the same in every u (256 u is a multiple of 8)
+  const bool in = k0 + 4 * (tid & 7) < d;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int idx = tid + 256 * u;
     const int row = idx >> 3;
     const int kk = 4 * (idx & 7);
-    sa[(kk + 0) * LDA + row] = r.q[u].x;
-    sa[(kk + 1) * LDA + row] = r.q[u].y;
-    sa[(kk + 2) * LDA + row] = r.q[u].z;
-    sa[(kk + 3) * LDA + row] = r.q[u].w;
-    sb[(kk + 0) * LDB + row] = r.x[u].x;
-    sb[(kk + 1) * LDB + row] = r.x[u].y;
-    sb[(kk + 2) * LDB + row] = r.x[u].z;
-    sb[(kk + 3) * LDB + row] = r.x[u].w;
+    const float4 q = in ? r.q[u] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 x = in ? r.x[u] : make_float4(0.f, 0.f, 0.f, 0.f);
+    sa[(kk + 0) * LDA + row] = q.x;
+    sa[(kk + 1) * LDA + row] = q.y;
+    sa[(kk + 2) * LDA + row] = q.z;
+    sa[(kk + 3) * LDA + row] = q.w;
+    sb[(kk + 0) * LDB + row] = x.x;
+    sb[(kk + 1) * LDB + row] = x.y;
+    sb[(kk + 2) * LDB + row] = x.z;
+    sb[(kk + 3) * LDB + row] = x.w;
   }
 }
 
 // The 128 x 128 block of a tile (accumulators of the four waves: row
 // wq + 16 rb + 4 (lane / 16) + r, column wx + 16 cb + lane % 16) as
-// approximate keys in the LDS tile.
+// approximate keys in the LDS tile, stored by column: tile[col * TLT + row].
+// A lane's four rows of one column are one 16-byte store, and the 16 lanes
+// of a store row fill the 64 banks once.
 __device__ __forceinline__ void tile_keys(const BfParams& p, const floatx4 (&acc)[4][4], float* tile,
                                           int64_t t0, int64_t r_end, int wq, int wx, int lane) {
 #pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
+  for (int cb = 0; cb < 4; ++cb) {
+    const int col = wx + cb * 16 + (lane & 15);
+    const int64_t xi = t0 + col;
+    const bool in = xi < r_end;
+    const float x2 = (p.metric == METRIC_IP || !in) ? 0.0f : p.x2[xi];
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-      const int col = wx + cb * 16 + (lane & 15);
-      const int64_t xi = t0 + col;
-      const float x2 = (p.metric == METRIC_IP || xi >= r_end) ? 0.0f : p.x2[xi];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = wq + rb * 16 + 4 * (lane >> 4) + r;
-        const float dot = acc[rb][cb][r];
-        float key = __builtin_inff();
-        if (xi < r_end) key = (p.metric == METRIC_IP) ? -dot : x2 - 2.0f * dot;
-        tile[row * TLD + col] = key;
+    for (int rb = 0; rb < 4; ++rb) {
+      const int row0 = wq + rb * 16 + 4 * (lane >> 4);
+      float4 k4;
+      const floatx4 a = acc[rb][cb];
+      if (p.metric == METRIC_IP) {
+        k4 = make_float4(-a[0], -a[1], -a[2], -a[3]);
+      } else {
+        k4 = make_float4(x2 - 2.0f * a[0], x2 - 2.0f * a[1], x2 - 2.0f * a[2], x2 - 2.0f * a[3]);
       }
+      if (!in) k4 = make_float4(__builtin_inff(), __builtin_inff(), __builtin_inff(), __builtin_inff());
+      *(float4*)(tile + col * TLT + row0) = k4;
     }
+  }
 }
 
 // Merge the key tile into the per-query lists (each wave its 32 queries).
 __device__ __forceinline__ void tile_merge(const BfParams& p, const float* tile, float (*lk)[KC],
                                            int (*li)[KC], int64_t q0, int64_t t0, int64_t r_end,
                                            int wave, int lane) {
-  // each wave merges its 32 queries, 64 columns at a time.  First every
-  // lane screens one (query, half tile) against that query's admission
-  // entry; only the flagged pairs take the wave-wide path (a later merge
-  // only lowers the entry, so an unflagged pair stays out)
+  // First every lane screens one (query, half tile) against that query's
+  // admission entry: lane l takes query row wave * 32 + l % 32 and half
+  // l / 32, the second half starting 8 columns on so that the two halves
+  // read different banks.  Only the flagged pairs take the wave-wide path
+  // (a later merge only lowers the entry, so an unflagged pair stays out).
   static_assert(BN == 128 && BM / 4 == 32, "one lane per (query, half tile) of the wave");
   bool hit = false;
   {
-    const int row = wave * (BM / 4) + (lane >> 1);
-    const int c0 = (lane & 1) * 64;
+    const int row = wave * (BM / 4) + (lane & 31);
+    const int half = lane >> 5;
     if (q0 + row < p.nq) {
       const float thr_k = lk[row][p.admit - 1];
       const int thr_i = li[row][p.admit - 1];
       for (int c = 0; c < 64; ++c) {
-        const int col = c0 + c;
+        const int col = half * 64 + ((c + 8 * half) & 63);
         const int id = (t0 + col < r_end) ? (int)(t0 + col) : 0x7FFFFFFF;
-        hit = hit | kid_less(tile[row * TLD + col], id, thr_k, thr_i);
+        hit = hit | kid_less(tile[col * TLT + row], id, thr_k, thr_i);
       }
     }
   }
   for (uint64_t todo = __ballot(hit); todo; todo &= todo - 1) {
     const int j = __builtin_ctzll(todo);
-    const int row = wave * (BM / 4) + (j >> 1);
-    const int col = (j & 1) * 64 + lane;
+    const int row = wave * (BM / 4) + (j & 31);
+    const int col = (j >> 5) * 64 + lane;
     const float thr_k = lk[row][p.admit - 1];
     const int thr_i = li[row][p.admit - 1];
-    float k = tile[row * TLD + col];
+    float k = tile[col * TLT + row];
     // columns past the range are empty entries (+inf, largest id)
     int id = (t0 + col < r_end) ? (int)(t0 + col) : 0x7FFFFFFF;
     const bool keep = kid_less(k, id, thr_k, thr_i);
@@ -291,7 +309,7 @@ __device__ __forceinline__ void lists_out(const BfParams& p, float (*lk)[KC], in
 }
 
 __global__ void __launch_bounds__(256) bf_tiles(BfParams p) {
-  __shared__ float stage[kStageFloats];   // [2][BK][LDA] queries, [2][BK][LDB] rows; later the key tile
+  __shared__ __align__(16) float stage[kStageFloats];   // [2][BK][LDA] queries, [2][BK][LDB] rows; later the key tile
   __shared__ float lk[BM][KC];
   __shared__ int li[BM][KC];
 
@@ -319,7 +337,7 @@ __global__ void __launch_bounds__(256) bf_tiles(BfParams p) {
   if (r_begin < r_end) load_stage(p, q0, r_begin, r_end, 0, regs);
   for (int64_t t0 = r_begin; t0 < r_end; t0 += BN) {
     __syncthreads();                      // the previous tile's keys have been read
-    store_stage(sa, sb, regs);
+    store_stage(sa, sb, regs, 0, p.d);
     __syncthreads();
     floatx4 acc[4][4];
 #pragma unroll
@@ -345,7 +363,7 @@ __global__ void __launch_bounds__(256) bf_tiles(BfParams p) {
           for (int cb = 0; cb < 4; ++cb)
             acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[rb], bv[cb], acc[rb][cb], 0, 0, 0);
       }
-      if (s + 1 < nst) store_stage(sa + (buf ^ 1) * (BK * LDA), sb + (buf ^ 1) * (BK * LDB), regs);
+      if (s + 1 < nst) store_stage(sa + (buf ^ 1) * (BK * LDA), sb + (buf ^ 1) * (BK * LDB), regs, (s + 1) * BK, p.d);
       __syncthreads();
     }
     tile_keys(p, acc, tile, t0, r_end, wq, wx, lane);
@@ -378,43 +396,46 @@ __global__ void bf_half(const float* src, int64_t count, uint16_t* dst) {
 }
 
 // One stage (64 dimensions from k0) of the query block and a base tile: 256
-// rows (queries first) of 8 16-byte chunks, 8 chunks per thread, zero outside
-// the matrices (d is a multiple of 8: a chunk is wholly in or out).
+// rows (queries first) of 8 16-byte chunks, 8 chunks per thread (d is a
+// multiple of 8: a chunk is wholly in or out).  Unconditional loads as in
+// load_stage: rows past the matrices read their last row, chunks past d
+// chunk 0, zeroed when stored.
 struct StageRegsH {
   uint4 v[8];
 };
 
 __device__ __forceinline__ void load_stage_h(const BfParams& p, int64_t q0, int64_t t0,
                                              int64_t r_end, int k0, StageRegsH& r) {
+  int k = k0 + 8 * (threadIdx.x & 7);     // the same in every u
+  k = k < p.d ? k : 0;
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
-    const int idx = threadIdx.x + 256 * u;
-    const int row = idx >> 3;
-    const int k = k0 + 8 * (idx & 7);
-    const uint16_t* src = nullptr;
-    if (row < BM) {
-      const int64_t qi = q0 + row;
-      if (qi < p.nq && k < p.d) src = p.Qh + qi * p.d + k;
+    const int row = (int)(threadIdx.x + 256 * u) >> 3;   // u < 4: queries, else rows
+    const uint16_t* src;
+    if (u < 4) {
+      const int64_t qi = q0 + row < p.nq ? q0 + row : p.nq - 1;
+      src = p.Qh + qi * p.d + k;
     } else {
-      const int64_t xi = t0 + (row - BM);
-      if (xi < r_end && k < p.d) src = p.Xh + xi * p.d + k;
+      const int64_t xi = t0 + (row - BM) < r_end ? t0 + (row - BM) : r_end - 1;
+      src = p.Xh + xi * p.d + k;
     }
-    r.v[u] = src ? *(const uint4*)src : make_uint4(0u, 0u, 0u, 0u);
+    r.v[u] = *(const uint4*)src;
   }
 }
 
-__device__ __forceinline__ void store_stage_h(uint16_t* sbuf, const StageRegsH& r) {
+__device__ __forceinline__ void store_stage_h(uint16_t* sbuf, const StageRegsH& r, int k0, int d) {
+  const bool in = k0 + 8 * (threadIdx.x & 7) < d;
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
     const int idx = threadIdx.x + 256 * u;
-    *(uint4*)(sbuf + (idx >> 3) * LDH + 8 * (idx & 7)) = r.v[u];
+    *(uint4*)(sbuf + (idx >> 3) * LDH + 8 * (idx & 7)) = in ? r.v[u] : make_uint4(0u, 0u, 0u, 0u);
   }
 }
 
 // bf_tiles with FP16 operands on v_mfma_f32_16x16x32_f16: the same blocks,
 // lists, admission and output, 64 dimensions per stage.
 __global__ void __launch_bounds__(256) bf_tiles_h(BfParams p) {
-  __shared__ float stage[kStageFloats];   // [2][256 rows][LDH] halves; later the key tile
+  __shared__ __align__(16) float stage[kStageFloats];   // [2][256 rows][LDH] halves; later the key tile
   __shared__ float lk[BM][KC];
   __shared__ int li[BM][KC];
 
@@ -441,7 +462,7 @@ __global__ void __launch_bounds__(256) bf_tiles_h(BfParams p) {
   if (r_begin < r_end) load_stage_h(p, q0, r_begin, r_end, 0, regs);
   for (int64_t t0 = r_begin; t0 < r_end; t0 += BN) {
     __syncthreads();                      // the previous tile's keys have been read
-    store_stage_h(sh, regs);
+    store_stage_h(sh, regs, 0, p.d);
     __syncthreads();
     floatx4 acc[4][4];
 #pragma unroll
@@ -471,7 +492,7 @@ __global__ void __launch_bounds__(256) bf_tiles_h(BfParams p) {
           for (int cb = 0; cb < 4; ++cb)
             acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[rb], bv[cb], acc[rb][cb], 0, 0, 0);
       }
-      if (st + 1 < nst) store_stage_h(sh + (buf ^ 1) * (2 * BM * LDH), regs);
+      if (st + 1 < nst) store_stage_h(sh + (buf ^ 1) * (2 * BM * LDH), regs, (st + 1) * BKH, p.d);
       __syncthreads();
     }
     tile_keys(p, acc, tile, t0, r_end, wq, wx, lane);
