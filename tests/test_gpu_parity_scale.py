@@ -41,8 +41,7 @@ def load_graph(tag):
     return oracle.Graph.load(p)
 
 
-@pytest.mark.parametrize("tag,n,nq", [("splade1m", 1_000_000, 10_000),
-                                       ("splade1m_n200000", 200_000, 1000)])
+@pytest.mark.parametrize("tag,n,nq", [("splade1m", 1_000_000, 10_000)])
 def test_sparse_at_size(tag, n, nq):
     g = load_graph(tag)
     spec = synth.WORKLOADS["splade1m"]
