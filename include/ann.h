@@ -743,6 +743,21 @@ int ann_version(void);
 /* Number of visible GPUs (0 if none); does not fail. */
 int ann_device_count(void);
 
+/*
+ * Invariant checks of the search kernels, in a library built with
+ * ANN_DEBUG_CHECKS (libann_debug.so beside libann.so; slower, for tests).
+ * Between expansions every workgroup checks its beam (the sorted list and
+ * insert buffer of the layer-0 search): each strictly ascending in (key, id),
+ * so its ids unique; |W| <= ef after the cut; every id inside [0, n); every
+ * entry before the scan position expanded; an expansion's candidate counts
+ * at most 64.  A violation sets a bit of a word the index holds (1 size, 2
+ * list order, 4 buffer order, 8 id range, 16 scan position, 32 counts); the
+ * kernels never trap.  ann_debug_flags waits for the device, copies the word
+ * to *out and, when clear is nonzero, zeroes it.  Without ANN_DEBUG_CHECKS it
+ * returns ANN_EUNSUP with *out = 0.
+ */
+int ann_debug_flags(const ann_index* ix, uint32_t* out, int32_t clear);
+
 #ifdef __cplusplus
 }
 #endif

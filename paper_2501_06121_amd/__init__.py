@@ -131,6 +131,7 @@ SIGNATURES = {
     "ann_server_destroy": ([P], C.c_int),
     "ann_last_error": ([], C.c_char_p),
     "ann_version": ([], C.c_int),
+    "ann_debug_flags": ([P, C.POINTER(C.c_uint32), C.c_int32], C.c_int),
     "ann_device_count": ([], C.c_int),
 }
 
@@ -714,6 +715,14 @@ class Server:
 
 def ann_version():
     return lib().ann_version()
+
+
+def ann_debug_flags(index, clear=True):
+    """Invariant-violation bits of a library built with ANN_DEBUG_CHECKS
+    (libann_debug.so); raises AnnError (ANN_EUNSUP) for the regular one."""
+    out = C.c_uint32(0)
+    _check(lib().ann_debug_flags(index.handle, C.byref(out), 1 if clear else 0))
+    return out.value
 
 
 def ann_device_count():

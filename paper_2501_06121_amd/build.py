@@ -43,8 +43,11 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
-def build(verbose: bool = False, jobs: int | None = None, defines=()) -> str:
-    """Compile every source to an object, then link libann.so."""
+DEBUG_LIB = os.path.join(PKG, "libann_debug.so")
+
+
+def build(verbose: bool = False, jobs: int | None = None, defines=(), out: str | None = None) -> str:
+    """Compile every source to an object, then link libann.so (or `out`)."""
     srcs = sources()
     extra = [f"-D{d}" for d in defines]
     tmpdir = tempfile.mkdtemp(prefix="annbuild_")
@@ -62,19 +65,26 @@ def build(verbose: bool = False, jobs: int | None = None, defines=()) -> str:
 
     with ThreadPoolExecutor(jobs or min(len(srcs), os.cpu_count() or 1)) as ex:
         list(ex.map(compile_one, zip(srcs, objs)))
-    tmp_lib = LIB + ".tmp"
+    target = out or LIB
+    tmp_lib = target + ".tmp"
     rt = hip_runtime_dir()
     cmd = ["g++", "-shared", "-fPIC", "-o", tmp_lib, *objs, f"-L{rt}", "-l:libamdhip64.so",
            f"-Wl,-rpath,{rt}", "-Wl,--no-undefined", "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp_lib, LIB)
+    os.replace(tmp_lib, target)
     for o in objs:
         os.remove(o)
     os.rmdir(tmpdir)
-    return LIB
+    return target
+
+
+def build_debug(verbose: bool = False, jobs: int | None = None) -> str:
+    """libann_debug.so: the same library with the kernels' invariant checks."""
+    return build(verbose, jobs, defines=("ANN_DEBUG_CHECKS",), out=DEBUG_LIB)
 
 
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_debug(verbose=True))

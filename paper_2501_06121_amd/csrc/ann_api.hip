@@ -246,6 +246,7 @@ int make_params(const ann_index* ix, const ann_batch* b, SearchParams* P) {
   }
   if (b->nq > INT32_MAX) return fail(ANN_EINVAL, "nq above 2^31 - 1");
   std::memset(P, 0, sizeof *P);
+  P->debug = ix->debug;
   P->mode = mode;
   P->metric = ix->metric;
   P->d = ix->d;
@@ -395,6 +396,21 @@ const char* ann_last_error(void) { return g_err.c_str(); }
 
 int ann_version(void) { return 1; }
 
+int ann_debug_flags(const ann_index* ix, uint32_t* out, int32_t clear) {
+  if (!ix || !out) return fail(ANN_EINVAL, "NULL argument");
+#ifdef ANN_DEBUG_CHECKS
+  HIP_OR_RETURN(hipSetDevice(ix->device), "hipSetDevice");
+  HIP_OR_RETURN(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  HIP_OR_RETURN(hipMemcpy(out, ix->debug, sizeof(uint32_t), hipMemcpyDeviceToHost), "hipMemcpy");
+  if (clear) HIP_OR_RETURN(hipMemset(ix->debug, 0, sizeof(uint32_t)), "hipMemset");
+  return ANN_OK;
+#else
+  (void)clear;
+  *out = 0;
+  return fail(ANN_EUNSUP, "this library was built without ANN_DEBUG_CHECKS");
+#endif
+}
+
 int ann_device_count(void) {
   int c = 0;
   if (hipGetDeviceCount(&c) != hipSuccess) return 0;
@@ -419,6 +435,10 @@ int ann_index_create(const ann_index_desc* D, int device, ann_index** out) {
   if (prop.maxSharedMemoryPerMultiProcessor > 0)
     ix->lds_limit = std::max(ix->lds_limit, std::min<size_t>(prop.maxSharedMemoryPerMultiProcessor, 160 * 1024));
   HIP_OR_RETURN(hipStreamCreateWithFlags(&ix->stream, hipStreamNonBlocking), "hipStreamCreate");
+#ifdef ANN_DEBUG_CHECKS
+  HIP_OR_RETURN(hipMalloc((void**)&ix->debug, sizeof(uint32_t)), "hipMalloc");
+  HIP_OR_RETURN(hipMemset(ix->debug, 0, sizeof(uint32_t)), "hipMemset");
+#endif
   ix->n = D->n; ix->d = D->d; ix->metric = D->metric; ix->M = D->M; ix->M0 = D->M0;
   ix->max_level = D->max_level; ix->entry = D->entry_point; ix->n_upper_lists = D->n_upper_lists;
   const size_t n = (size_t)D->n, d = (size_t)D->d;
@@ -479,6 +499,7 @@ int ann_index_free(ann_index* ix) {
   ix->ws.release();
   if (ix->bf_scratch) (void)hipFree(ix->bf_scratch);
   if (ix->bf_xh) (void)hipFree(ix->bf_xh);
+  if (ix->debug) (void)hipFree(ix->debug);
   if (ix->bf_done) (void)hipEventDestroy(ix->bf_done);
   void* ptrs[] = {ix->adj0, ix->upper_off, ix->upper_adj, ix->x_f32, ix->x_f16, ix->x_bf16,
                   ix->x_fp8, ix->fp8_scale, ix->pq_cb, ix->pq_codes, ix->sp_ptr, ix->sp_ids,

@@ -76,6 +76,7 @@ struct ann_index {
   hipEvent_t bf_done = nullptr;      // recorded after the last brute-force call's kernels
   bool bf_used = false;
   void* bf_xh = nullptr;             // the rows' FP16 copy for the half-precision brute-force pass
+  uint32_t* debug = nullptr;         // ANN_DEBUG_CHECKS builds: the kernels' invariant-violation bits
   ann_launch_cfg cfg[6] = {};
   std::mutex mu;
   ann::Workspace ws;                 // used by ann_search / ann_search_ex

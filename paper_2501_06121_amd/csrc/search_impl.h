@@ -920,6 +920,57 @@ __device__ __forceinline__ void log_visited(const SearchParams& p, int slot, int
   st.visited += cnt;
 }
 
+// ---- invariant checks (builds with ANN_DEBUG_CHECKS only) ------------------
+//
+// The beam's invariants, checked by the whole workgroup between expansions;
+// a violation sets a bit of *p.debug (never a trap):
+//   1  |W| = w + wb above ef (after the cut), or a length outside its array
+//   2  the list L[0, w) not strictly ascending in (key, id)
+//   4  the insert buffer B[0, wb) not strictly ascending in (key, id)
+//   8  an id outside [0, n)
+//  16  an entry before the scan position (hint, hint_b) not expanded
+//  32  an expansion's candidate counts out of range (m > 64 or kept > m)
+// Strict order under (key, id) also makes the ids of each array unique.
+enum { kDbgSize = 1, kDbgListOrder = 2, kDbgBufOrder = 4, kDbgId = 8, kDbgHint = 16, kDbgCount = 32 };
+
+__device__ __forceinline__ void debug_flag(const SearchParams& p, uint32_t bits) {
+#ifdef ANN_DEBUG_CHECKS
+  if (bits && p.debug) atomicOr(p.debug, bits);
+#else
+  (void)p;
+  (void)bits;
+#endif
+}
+
+template <bool GLIST>
+__device__ void debug_check_beam(const SearchParams& p, const Lds& s, const List& L, int w, int wb,
+                                 int ef, int hint, int hint_b) {
+#ifdef ANN_DEBUG_CHECKS
+  __syncthreads();
+  uint32_t bad = 0;
+  const int wcap = p.wbuf > 0 ? p.wbuf : 0;
+  if (w < 0 || wb < 0 || w > p.ef_cap || wb > wcap || w + wb > ef) bad |= kDbgSize;
+  const int wl = w < p.ef_cap ? w : p.ef_cap;
+  const int bl = wb < wcap ? wb : wcap;
+  for (int i = threadIdx.x; i < wl; i += blockDim.x) {
+    const uint32_t id = L.id[i] & kIdMask;
+    if (id >= (uint64_t)p.n) bad |= kDbgId;
+    if (i + 1 < wl && !kid_lt(L.key[i], id, L.key[i + 1], L.id[i + 1] & kIdMask)) bad |= kDbgListOrder;
+    if (i < hint && !(L.id[i] & kExpanded)) bad |= kDbgHint;
+  }
+  for (int i = threadIdx.x; i < bl; i += blockDim.x) {
+    const uint32_t id = s.bid[i] & kIdMask;
+    if (id >= (uint64_t)p.n) bad |= kDbgId;
+    if (i + 1 < bl && !kid_lt(s.bkey[i], id, s.bkey[i + 1], s.bid[i + 1] & kIdMask)) bad |= kDbgBufOrder;
+    if (i < hint_b && !(s.bid[i] & kExpanded)) bad |= kDbgHint;
+  }
+  debug_flag(p, bad);
+  __syncthreads();
+#else
+  (void)p; (void)s; (void)L; (void)w; (void)wb; (void)ef; (void)hint; (void)hint_b;
+#endif
+}
+
 template <class Policy, bool GLIST>
 __device__ __forceinline__ void run_query(const SearchParams& p, const Lds& s, Policy& pol, int slot, int64_t q) {
   const int lane = lane_id();
@@ -1020,9 +1071,12 @@ __device__ __forceinline__ void run_query(const SearchParams& p, const Lds& s, P
   int hint = 0, hint_b = 0;
   ListCache lc{-1, -1, 0.0f, kExpanded};
   while (true) {
+    // (the sizes before the cut may exceed ef by one expansion's entries)
+    debug_check_beam<GLIST>(p, s, L, w, wb, w + wb > ef ? w + wb : ef, hint, hint_b);
     // cut to ef, best unexpanded entry and worst entry of W (all waves
     // compute them from the same state)
     const Head hd = beam_head<GLIST>(s, L, w, wb, ef, hint, hint_b, buffered, lc);
+    debug_check_beam<GLIST>(p, s, L, w, wb, ef, 0, 0);
     const int pm = hd.pm, pb = hd.pb;
     if (pm < 0 && pb < 0) break;
     const bool from_buf = pb >= 0 && (pm < 0 || kid_lt(s.bkey[pb], s.bid[pb] & kIdMask, hd.mk, hd.mi));
@@ -1053,6 +1107,7 @@ __device__ __forceinline__ void run_query(const SearchParams& p, const Lds& s, P
       else L.id[pm] = (uint32_t)c | kExpanded;
     }
     const int m = s.ctl[cm];
+    if (tid == 0 && m > 64) debug_flag(p, kDbgCount);
     if (m == 0) continue;
     pol.score(p, s, m);
     __syncthreads();
@@ -1091,6 +1146,7 @@ __device__ __forceinline__ void run_query(const SearchParams& p, const Lds& s, P
     }
     __syncthreads();
     const int mnew = s.ctl[cm];
+    if (tid == 0 && mnew > m) debug_flag(p, kDbgCount);
     if (mnew > 0) {
       if (!buffered) {
         w = merge_sorted<4>(L.key, L.id, w, ef, s.ckey, (const uint32_t*)s.cid, mnew, &s.ctl[CTL_R0],
@@ -1132,6 +1188,7 @@ __device__ __forceinline__ void run_query(const SearchParams& p, const Lds& s, P
     }
     wb = 0;
   }
+  debug_check_beam<GLIST>(p, s, L, w, wb, ef, 0, 0);
   if (wave == 0 && lane == 0) {
     s.ctl[CTL_VISITED] = st.visited;
     s.ctl[CTL_VLOG] = st.vlog_n;

@@ -128,6 +128,7 @@ struct SearchParams {
   int vlog_cap;
   int32_t* counter;
   RingArgs ring;
+  uint32_t* debug;       // builds with ANN_DEBUG_CHECKS: invariant violations (bits), else unused
 };
 
 // Entries of the sparse query's hash table in LDS (at most half filled).
