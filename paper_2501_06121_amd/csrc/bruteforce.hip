@@ -158,7 +158,25 @@ struct BfParams {
   const int32_t* redo;   // optional [nq]: only blocks with a query whose flag is 0 are scanned
   const uint16_t* Xh;    // FP16 copies (bf_tiles_h): rows [n][d], queries [nq][d]
   const uint16_t* Qh;
+  uint32_t* bound;       // optional [nq]: shared admission bounds (ordered key bits, see below)
 };
+
+// Shared admission bounds.  A range's list, once it holds `admit` entries,
+// has its admit-th key at or above the admit-th best key over all rows, so
+// the smallest such key published by the workgroups scanning the same
+// queries in other ranges bounds what any range still needs: a row whose key
+// is not below it can be left out (it sorts after the merged list's admit-th
+// entry, which the certificate already accounts for).  Keys are kept as
+// order-preserving unsigned bits so that atomicMin applies; all ones (the
+// initial fill) means no bound.
+__device__ __forceinline__ uint32_t key_bits(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float bits_key(uint32_t o) {
+  if (o == 0xFFFFFFFFu) return __builtin_inff();
+  return __uint_as_float((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o);
+}
 
 // Whether this workgroup's block of BM queries has work: without a redo mask
 // always; with one, when some query of the block was not certified.
@@ -250,9 +268,11 @@ __device__ __forceinline__ void tile_keys(const BfParams& p, const floatx4 (&acc
 }
 
 // Merge the key tile into the per-query lists (each wave its 32 queries).
+// bnd: the shared bound of this lane's query (row wave * 32 + lane % 32), +inf
+// without one; rows need a key strictly below it as well.
 __device__ __forceinline__ void tile_merge(const BfParams& p, const float* tile, float (*lk)[KC],
                                            int (*li)[KC], int64_t q0, int64_t t0, int64_t r_end,
-                                           int wave, int lane) {
+                                           int wave, int lane, float bnd = __builtin_inff()) {
   // First every lane screens one (query, half tile) against that query's
   // admission entry: lane l takes query row wave * 32 + l % 32 and half
   // l / 32, the second half starting 8 columns on so that the two halves
@@ -269,7 +289,8 @@ __device__ __forceinline__ void tile_merge(const BfParams& p, const float* tile,
       for (int c = 0; c < 64; ++c) {
         const int col = half * 64 + ((c + 8 * half) & 63);
         const int id = (t0 + col < r_end) ? (int)(t0 + col) : 0x7FFFFFFF;
-        hit = hit | kid_less(tile[col * TLT + row], id, thr_k, thr_i);
+        const float key = tile[col * TLT + row];
+        hit = hit | (kid_less(key, id, thr_k, thr_i) && key < bnd);
       }
     }
   }
@@ -279,10 +300,11 @@ __device__ __forceinline__ void tile_merge(const BfParams& p, const float* tile,
     const int col = (j >> 5) * 64 + lane;
     const float thr_k = lk[row][p.admit - 1];
     const int thr_i = li[row][p.admit - 1];
+    const float rb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bnd), j & 31));
     float k = tile[col * TLT + row];
     // columns past the range are empty entries (+inf, largest id)
     int id = (t0 + col < r_end) ? (int)(t0 + col) : 0x7FFFFFFF;
-    const bool keep = kid_less(k, id, thr_k, thr_i);
+    const bool keep = kid_less(k, id, thr_k, thr_i) && k < rb;
     const uint64_t km = __ballot(keep);
     if (!km) continue;
     if (__builtin_popcountll(km) > 8) {
@@ -434,10 +456,19 @@ __device__ __forceinline__ void store_stage_h(uint16_t* sbuf, const StageRegsH& 
 
 // bf_tiles with FP16 operands on v_mfma_f32_16x16x32_f16: the same blocks,
 // lists, admission and output, 64 dimensions per stage.
+// Hits of one tile, found in registers: the (query row, column, key) of every
+// key at or below its query's threshold (list admission entry and shared
+// bound of the previous tile: a superset of what the lists admit now).
+constexpr int kHitCap = 1024;
+
 __global__ void __launch_bounds__(256) bf_tiles_h(BfParams p) {
   __shared__ __align__(16) float stage[kStageFloats];   // [2][256 rows][LDH] halves; later the key tile
   __shared__ float lk[BM][KC];
   __shared__ int li[BM][KC];
+  __shared__ float thr_s[BM];             // per query row: min(admission key, shared bound)
+  __shared__ int hit_n;
+  __shared__ int hit_rc[kHitCap];         // row * BN + column
+  __shared__ float hit_k[kHitCap];
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
@@ -457,6 +488,8 @@ __global__ void __launch_bounds__(256) bf_tiles_h(BfParams p) {
     lk[i / KC][i % KC] = __builtin_inff();
     li[i / KC][i % KC] = 0x7FFFFFFF;
   }
+  if (tid < BM) thr_s[tid] = __builtin_inff();
+  if (tid == 0) hit_n = 0;
 
   StageRegsH regs;
   if (r_begin < r_end) load_stage_h(p, q0, r_begin, r_end, 0, regs);
@@ -495,10 +528,88 @@ __global__ void __launch_bounds__(256) bf_tiles_h(BfParams p) {
       if (st + 1 < nst) store_stage_h(sh + (buf ^ 1) * (2 * BM * LDH), regs, (st + 1) * BKH, p.d);
       __syncthreads();
     }
-    tile_keys(p, acc, tile, t0, r_end, wq, wx, lane);
+    // the shared bound of this lane's query, read before the next stage's
+    // loads are issued (a load waited for after them would wait for them too)
+    const int brow = wave * (BM / 4) + (lane & 31);
+    const int64_t bq = q0 + brow < p.nq ? q0 + brow : p.nq - 1;
+    const uint32_t bseen = p.bound ? p.bound[bq] : 0xFFFFFFFFu;
+    const float bnd = bits_key(bseen);
+    // the keys that may enter a list go to the hit list; the rest of the
+    // tile is never written out
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      const int col = wx + cb * 16 + (lane & 15);
+      const int64_t xi = t0 + col;
+      const bool in = xi < r_end;
+      const float x2 = (p.metric == METRIC_IP || !in) ? 0.0f : p.x2[xi];
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = wq + rb * 16 + 4 * (lane >> 4) + r;
+          const float dot = acc[rb][cb][r];
+          const float key = (p.metric == METRIC_IP) ? -dot : x2 - 2.0f * dot;
+          if (in && key <= thr_s[row]) {
+            const int slot = atomicAdd(&hit_n, 1);
+            if (slot < kHitCap) { hit_rc[slot] = row * BN + col; hit_k[slot] = key; }
+          }
+        }
+    }
     __syncthreads();
-    if (t0 + BN < r_end) load_stage_h(p, q0, t0 + BN, r_end, 0, regs);
-    tile_merge(p, tile, lk, li, q0, t0, r_end, wave, lane);
+    const int nh = hit_n;
+    if (nh > kHitCap) {
+      // too many for the list (the first tiles of a range): the whole tile
+      // through LDS as before
+      tile_keys(p, acc, tile, t0, r_end, wq, wx, lane);
+      __syncthreads();
+      if (t0 + BN < r_end) load_stage_h(p, q0, t0 + BN, r_end, 0, regs);
+      tile_merge(p, tile, lk, li, q0, t0, r_end, wave, lane, bnd);
+    } else {
+      if (t0 + BN < r_end) load_stage_h(p, q0, t0 + BN, r_end, 0, regs);
+      // each wave inserts the hits of its 32 query rows, one row at a time
+      for (int base = 0; base < nh; base += 64) {
+        const int i = base + lane;
+        int row = -1;
+        float k = __builtin_inff();
+        int id = 0x7FFFFFFF;
+        if (i < nh) {
+          const int rc = hit_rc[i];
+          if ((rc / BN) / (BM / 4) == wave) {
+            row = rc / BN;
+            k = hit_k[i];
+            id = (int)(t0 + rc % BN);
+          }
+        }
+        for (uint64_t todo = __ballot(row >= 0); todo;) {
+          const int j = __builtin_ctzll(todo);
+          const int r = __builtin_amdgcn_readlane(row, j);
+          const uint64_t same = __ballot(row == r);
+          todo &= ~same;
+          const float rb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bnd), r & 31));
+          const bool keep = row == r && kid_less(k, id, lk[r][p.admit - 1], li[r][p.admit - 1]) && k < rb;
+          const uint64_t km = __ballot(keep);
+          if (!km) continue;
+          if (__builtin_popcountll(km) > 8) {
+            merge_list(lk[r], li[r], keep ? k : __builtin_inff(), keep ? id : 0x7FFFFFFF);
+          } else {
+            insert_few(lk[r], li[r], k, id, km);
+          }
+        }
+      }
+    }
+    // publish this range's admit-th key where it lowers the bound, and the
+    // threshold of the next tile's hit search
+    if (lane < 32) {
+      const float ka = lk[brow][p.admit - 1];
+      uint32_t nb = bseen;
+      if (p.bound && q0 + brow < p.nq && ka < __builtin_inff() && key_bits(ka) < bseen) {
+        atomicMin(&p.bound[bq], key_bits(ka));
+        nb = key_bits(ka);
+      }
+      thr_s[brow] = fminf(ka, bits_key(nb));
+    }
+    __syncthreads();
+    if (tid == 0) hit_n = 0;
   }
   __syncthreads();
   lists_out(p, lk, li, q0, range);
@@ -682,7 +793,7 @@ int bf_check(const ann_index* ix, const float* queries, int64_t nq, int32_t k, c
 int bf_launch(const ann_index* ix, const float* queries, int64_t nq, int32_t k, int64_t* out_ids,
               float* out_dists, int32_t* out_certified, hipStream_t st, int nranges, float* x2,
               float* ckey, int32_t* cid, bool norms, const uint16_t* xh = nullptr,
-              uint16_t* qh = nullptr, int32_t* hcert = nullptr) {
+              uint16_t* qh = nullptr, int32_t* hcert = nullptr, uint32_t* bound = nullptr) {
   if (norms) {
     hipLaunchKernelGGL(bf_norms, dim3((unsigned)ix->n), dim3(64), 0, st, ix->x_f32, ix->n, ix->d, x2);
     HIP_OR_RETURN(hipGetLastError(), "bf_norms launch");
@@ -697,7 +808,7 @@ int bf_launch(const ann_index* ix, const float* queries, int64_t nq, int32_t k, 
   // are not inserted (entries further down may then be stale).
   p.admit = std::min(KC, k + kRescore + 1);
   p.cand_key = ckey; p.cand_id = cid;
-  p.redo = nullptr; p.Xh = nullptr; p.Qh = nullptr;
+  p.redo = nullptr; p.Xh = nullptr; p.Qh = nullptr; p.bound = nullptr;
   const dim3 grid((unsigned)((nq + BM - 1) / BM), (unsigned)nranges);
   BfFinish f;
   f.X = ix->x_f32; f.n = ix->n; f.d = ix->d; f.metric = ix->metric; f.Q = queries; f.nq = nq;
@@ -710,8 +821,13 @@ int bf_launch(const ann_index* ix, const float* queries, int64_t nq, int32_t k, 
                        st, queries, cnt, qh);
     HIP_OR_RETURN(hipGetLastError(), "bf_half launch");
     p.Xh = xh; p.Qh = qh;
+    // no bound yet for any query (the FP32 pass below keeps none: its keys
+    // round differently)
+    HIP_OR_RETURN(hipMemsetAsync(bound, 0xFF, (size_t)nq * 4, st), "hipMemsetAsync");
+    p.bound = bound;
     hipLaunchKernelGGL(bf_tiles_h, grid, dim3(256), 0, st, p);
     HIP_OR_RETURN(hipGetLastError(), "bf_tiles_h launch");
+    p.bound = nullptr;
     f.half = 1; f.redo = nullptr; f.out_certified = hcert;
     hipLaunchKernelGGL(bf_finish, dim3((unsigned)nq), dim3(64), 0, st, f);
     HIP_OR_RETURN(hipGetLastError(), "bf_finish launch");
@@ -766,7 +882,8 @@ extern "C" int ann_bruteforce(const ann_index* cix, const float* queries, int64_
   hipStream_t st = stream ? (hipStream_t)stream : ix->stream;
   const int nranges = bf_ranges(ix->n, nq, ix->cu_count > 0 ? ix->cu_count : 256);
   // the half pass's extra scratch: the queries' FP16 copy and its certificates
-  const size_t half_extra = (((size_t)nq * ix->d * 2 + 255) & ~size_t(255)) + (size_t)nq * 4;
+  const size_t half_extra = (((size_t)nq * ix->d * 2 + 255) & ~size_t(255)) + (((size_t)nq * 4 + 255) & ~size_t(255)) +
+                            (size_t)nq * 4;
   const size_t need = bruteforce_scratch_bytes(ix->n, nq, nranges) + half_extra;
   if (!ix->bf_done)
     HIP_OR_RETURN(hipEventCreateWithFlags(&ix->bf_done, hipEventDisableTiming), "hipEventCreate");
@@ -791,9 +908,10 @@ extern "C" int ann_bruteforce(const ann_index* cix, const float* queries, int64_
   int32_t* cid = (int32_t*)(ckey + (size_t)nq * nranges * KC);
   uint16_t* qh = (uint16_t*)(base + bruteforce_scratch_bytes(ix->n, nq, nranges));
   int32_t* hcert = (int32_t*)((char*)qh + (((size_t)nq * ix->d * 2 + 255) & ~size_t(255)));
+  uint32_t* bound = (uint32_t*)((char*)hcert + (((size_t)nq * 4 + 255) & ~size_t(255)));
   const uint16_t* xh = half_rows(ix, st);
   rc = bf_launch(ix, queries, nq, k, out_ids, out_dists, out_certified, st, nranges, x2, ckey, cid,
-                 !ix->bf_norms_ready, xh, xh ? qh : nullptr, xh ? hcert : nullptr);
+                 !ix->bf_norms_ready, xh, xh ? qh : nullptr, xh ? hcert : nullptr, xh ? bound : nullptr);
   if (rc) return rc;
   ix->bf_norms_ready = true;
   HIP_OR_RETURN(hipEventRecord(ix->bf_done, st), "hipEventRecord");
