@@ -536,6 +536,11 @@ __global__ void __launch_bounds__(256) bf_tiles_h(BfParams p) {
     const float bnd = bits_key(bseen);
     // the keys that may enter a list go to the hit list; the rest of the
     // tile is never written out
+    float th[4][4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) th[rb][r] = thr_s[wq + rb * 16 + 4 * (lane >> 4) + r];
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) {
       const int col = wx + cb * 16 + (lane & 15);
@@ -549,7 +554,7 @@ __global__ void __launch_bounds__(256) bf_tiles_h(BfParams p) {
           const int row = wq + rb * 16 + 4 * (lane >> 4) + r;
           const float dot = acc[rb][cb][r];
           const float key = (p.metric == METRIC_IP) ? -dot : x2 - 2.0f * dot;
-          if (in && key <= thr_s[row]) {
+          if (in && key <= th[rb][r]) {
             const int slot = atomicAdd(&hit_n, 1);
             if (slot < kHitCap) { hit_rc[slot] = row * BN + col; hit_k[slot] = key; }
           }
