@@ -407,8 +407,10 @@ struct PQ {
         const uint8_t* cp = p.pq_codes + (size_t)(rid[u] < 0 ? 0 : rid[u]) * p.pq_stride;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
+          // unconditional (row 0, entry 0 where there is none; the code is
+          // then not used), so that the loads stay in flight together
           const int m = j + L * v;
-          code[u][v] = (rid[u] >= 0 && m < p.pq_m) ? (uint32_t)cp[m] : 0u;
+          code[u][v] = (uint32_t)cp[m < p.pq_m ? m : 0];
         }
       }
 #pragma unroll
@@ -512,15 +514,20 @@ struct Sparse {
       for (int64_t off = lane; off < most; off += 64) {
         uint32_t tid[U];
         float val[U];
+        // every load is issued unconditionally (past a document's end it
+        // reads a valid entry that is then ignored): loads under a per-lane
+        // condition are each waited for on the spot, which kept only one
+        // document's entries in flight
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int64_t j = b[u] + off;
-          tid[u] = (j < e[u]) ? (uint32_t)p.sp_ids[j] : kHashEmpty;
-          val[u] = (j < e[u]) ? p.sp_vals[j] : 0.0f;
+          const int64_t jc = j < e[u] ? j : (e[u] > b[u] ? e[u] - 1 : 0);
+          tid[u] = (uint32_t)p.sp_ids[jc];
+          val[u] = p.sp_vals[jc];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-          if (tid[u] != kHashEmpty) acc[u] = __builtin_fmaf(weight(s, tid[u]), val[u], acc[u]);
+          if (b[u] + off < e[u]) acc[u] = __builtin_fmaf(weight(s, tid[u]), val[u], acc[u]);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -1221,10 +1228,11 @@ __device__ __forceinline__ void run_query(const SearchParams& p, const Lds& s, P
         for (int u = 0; u < kRerankRows; ++u) {
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
+            // unconditional (row 0, chunk 0 where there is none: the sum is
+            // then skipped or not stored), so that the loads stay in flight
             const int g = tb + lane + 64 * t;
-            raw[u][t] = (rid[u] >= 0 && g < nch)
-                ? *(const uint4*)(p.x_f32 + (size_t)rid[u] * p.d + (size_t)g * 4)
-                : make_uint4(0u, 0u, 0u, 0u);
+            const size_t row = rid[u] >= 0 ? (size_t)rid[u] : 0;
+            raw[u][t] = *(const uint4*)(p.x_f32 + row * p.d + (size_t)(g < nch ? g : 0) * 4);
           }
         }
 #pragma unroll
