@@ -60,6 +60,41 @@ def test_half_pass_and_fp32_redo():
     assert np.all(cert != 0) and np.mean(cert == 1) > 0.9, np.bincount(cert)
 
 
+def test_values_beyond_the_fp16_range_take_the_fp32_tiles():
+    """A query with a value beyond the FP16 range is saturated in the FP16
+    pass, which then never certifies it: the FP32 tiles redo it (flag 1).
+    Rows with such values switch the FP16 pass off for the whole index."""
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((2000, 32)).astype(np.float32)
+    Q = rng.standard_normal((20, 32)).astype(np.float32)
+    Q[3, 7] = 1.0e5                        # beyond 65504
+    Q[11, 0] = -7.0e4
+    g = oracle.hnsw_build(X, "ip", 8, 32, np.zeros(X.shape[0]))
+    ref_ids, ref_k = oracle.bruteforce(oracle.dense_store(X, "ip"), X.shape[0], 10, Q=Q, kmode="canon")
+    ix = ann.ann_index_create(g, "ip", 32, x_f32=X)
+    try:
+        ids, d, cert = ann.ann_bruteforce(ix, torch.from_numpy(Q).to("cuda:0"), 10)
+        torch.cuda.synchronize()
+        ids, d, cert = ids.cpu().numpy(), d.cpu().numpy(), cert.cpu().numpy()
+    finally:
+        ix.close()
+    assert np.array_equal(ids, ref_ids) and np.array_equal(d, ref_k)
+    assert cert[3] == 1 and cert[11] == 1 and np.all(cert != 0)
+    # rows beyond the FP16 range (all scaled, so that the FP32 bound, which
+    # grows with the largest value, still separates the keys): FP32 tiles only
+    X2 = X * np.float32(1.0e5)
+    ref_ids, ref_k = oracle.bruteforce(oracle.dense_store(X2, "ip"), X2.shape[0], 10, Q=Q, kmode="canon")
+    ix = ann.ann_index_create(g, "ip", 32, x_f32=X2)
+    try:
+        ids, d, cert = ann.ann_bruteforce(ix, torch.from_numpy(Q).to("cuda:0"), 10)
+        torch.cuda.synchronize()
+        ids, d, cert = ids.cpu().numpy(), d.cpu().numpy(), cert.cpu().numpy()
+    finally:
+        ix.close()
+    assert np.array_equal(ids, ref_ids) and np.array_equal(d, ref_k)
+    assert np.all(cert == 1)
+
+
 def test_half_pass_certifies_the_mixture(gmm10k):
     X, Q, g = gmm10k["X"], gmm10k["Q"], gmm10k["graph"]
     ix = ann.ann_index_create(g, "l2", X.shape[1], x_f32=X)
