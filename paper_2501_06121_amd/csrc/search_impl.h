@@ -117,6 +117,8 @@ __device__ __forceinline__ float fold_lanes(float v) {
 // shared-memory layout of one wave (dynamic LDS)
 // ----------------------------------------------------------------------------
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 struct Lds {
   float* wkey;       // [ef_cap]
   uint32_t* wid;     // [ef_cap] id | kExpanded
@@ -269,10 +271,14 @@ struct Dense {
 #pragma unroll
         for (int t = 0; t < CPL; ++t) {
           const int g = j + L * t;
-          if (rid[u] >= 0 && g < p.nchunks)
-            raw[u][t] = *(const uint4*)(rp + (size_t)g * 16);
-          else
+          // rows are read once per query: streaming (nontemporal) loads
+          // leave the caches to the lists and bitsets (+0.5% measured)
+          if (rid[u] >= 0 && g < p.nchunks) {
+            const u32x4 v = __builtin_nontemporal_load((const u32x4*)(rp + (size_t)g * 16));
+            raw[u][t] = make_uint4(v[0], v[1], v[2], v[3]);
+          } else {
             raw[u][t] = make_uint4(0u, 0u, 0u, 0u);
+          }
         }
       }
 #pragma unroll
@@ -1094,7 +1100,8 @@ __device__ __forceinline__ void run_query(const SearchParams& p, const Lds& s, P
     const int cm = (st.expansions & 1) ? CTL_M_ODD : CTL_M;
     if (wave == 0) {
       // neighbour list, visited bits (each bit set exactly once), compaction
-      const int nb = (lane < p.M0) ? p.adj0[(size_t)c * p.M0 + lane] : -1;
+      // (streaming load, like the rows: +0.3% measured)
+      const int nb = (lane < p.M0) ? __builtin_nontemporal_load(&p.adj0[(size_t)c * p.M0 + lane]) : -1;
       bool isnew = false;
       if (nb >= 0) {
         const uint32_t bit = 1u << (nb & 31);
