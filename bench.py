@@ -496,6 +496,37 @@ def quant_rows(ann, torch, ix, mode, Qd, gt, g, X, efs, rerank, stream, pq_m):
     return rows
 
 
+def bruteforce_row(ann, torch, ix, Qd, k, stream, gt, n, d):
+    """One exact k-NN call over all queries, timed with events on its stream."""
+    try:
+        ann.ann_bruteforce(ix, Qd[:256], k)          # warm the row norms and scratch
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        bids, _, cert = ann.ann_bruteforce(ix, Qd, k, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+    except ann.AnnError as e:
+        log(f"bruteforce skipped: {e}")
+        return None
+    bms = e0.elapsed_time(e1)
+    flops = 2.0 * Qd.shape[0] * n * d
+    c = cert.cpu().numpy()
+    # the scan's contraction runs on FP16 matrix cores when that pass
+    # certifies the queries (flag 2), on FP32 ones for the rest (flag 1)
+    half = float((c == 2).mean())
+    peak = FP16_MFMA_PEAK if half > 0.5 else FP32_MFMA_PEAK
+    bf = {"ms": round(bms, 2), "tflops": round(flops / (bms / 1e3) / 1e12, 1),
+          "peak_tflops": peak, "peak_dtype": "f16" if half > 0.5 else "f32",
+          "frac": round(flops / (bms / 1e3) / 1e12 / peak, 4),
+          "certified": float((c != 0).mean()), "certified_by_fp16_pass": half,
+          "recall@10_vs_oracle_gt": recall(bids.cpu().numpy(), gt, k) if gt is not None else None}
+    log(f"bruteforce: {bms:.1f} ms, {bf['tflops']} TFLOP/s, certified {bf['certified']:.4f}, "
+        f"agreement with oracle GT {bf['recall@10_vs_oracle_gt']}")
+    return bf
+
+
 def host_threads():
     """Threads the host gives this process (OMP_NUM_THREADS when set, else the CPUs it may use)."""
     env = os.environ.get("OMP_NUM_THREADS")
@@ -593,6 +624,8 @@ def main():
     ap.add_argument("--ivf-only", action="store_true",
                     help="time only the IVF search at its chosen nprobe (for profiling)")
     ap.add_argument("--no-ivf", action="store_true")
+    ap.add_argument("--bf-only", action="store_true",
+                    help="time only the exact k-NN scan over all queries (for profiling)")
     ap.add_argument("--serve-mix", action="store_true",
                     help="only the serving mix: 10M x 96 graph built on the device, Poisson "
                     "arrivals at 5k-50k QPS with mixed k and ef; prints one JSON line")
@@ -642,6 +675,10 @@ def main():
     dev = "cuda:0"
     Qd = torch.from_numpy(Q).to(dev)
     stream = torch.cuda.Stream()
+    if a.bf_only:
+        print(json.dumps({"bruteforce_mfma": bruteforce_row(ann, torch, ix, Qd, k, stream, gt,
+                                                            X.shape[0], d)}), flush=True)
+        return
 
     ivf_data = load_ivf(a.workload)
     ivf = None
@@ -809,32 +846,7 @@ def main():
         log(f"bf16+rerank{a.rerank} ef={ef}: {msb:.2f} ms/step, {bf16_row['qps']:.0f} QPS, recall {recb}")
 
     # exact k-NN on matrix cores (ground truth path): one launch, all queries
-    bf = None
-    try:
-        ann.ann_bruteforce(ix, Qd[:256], k)          # warm the row norms and scratch
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        bids, _, cert = ann.ann_bruteforce(ix, Qd, k, stream=stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        bms = e0.elapsed_time(e1)
-        flops = 2.0 * Q.shape[0] * X.shape[0] * d
-        c = cert.cpu().numpy()
-        # the scan's contraction runs on FP16 matrix cores when that pass
-        # certifies the queries (flag 2), on FP32 ones for the rest (flag 1)
-        half = float((c == 2).mean())
-        peak = FP16_MFMA_PEAK if half > 0.5 else FP32_MFMA_PEAK
-        bf = {"ms": round(bms, 2), "tflops": round(flops / (bms / 1e3) / 1e12, 1),
-              "peak_tflops": peak, "peak_dtype": "f16" if half > 0.5 else "f32",
-              "frac": round(flops / (bms / 1e3) / 1e12 / peak, 4),
-              "certified": float((c != 0).mean()), "certified_by_fp16_pass": half,
-              "recall@10_vs_oracle_gt": recall(bids.cpu().numpy(), gt, k) if gt is not None else None}
-        log(f"bruteforce: {bms:.1f} ms, {bf['tflops']} TFLOP/s, certified {bf['certified']:.4f}, "
-            f"agreement with oracle GT {bf['recall@10_vs_oracle_gt']}")
-    except ann.AnnError as e:
-        log(f"bruteforce skipped: {e}")
+    bf = bruteforce_row(ann, torch, ix, Qd, k, stream, gt, X.shape[0], d)
 
     # IVF index over the same rows (an index family beside the graph)
     ivf_rows = None
