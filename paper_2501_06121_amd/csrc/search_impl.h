@@ -132,8 +132,7 @@ struct Lds {
   float* q;          // [d_pad] FP32 query (rerank, PQ tables)
   float* rk;         // [ef_cap] rerank keys
   float* lut;        // [pq_m * 256] PQ lookup table
-  uint32_t* hkey;    // [kHashSlots] sparse query terms
-  float* hval;       // [kHashSlots]
+  uint2* htab;       // [kHashSlots] sparse query terms: (term, weight bits)
   int64_t* sb;       // [64] sparse row extents of one expansion
   int64_t* se;       // [64]
   int32_t* ctl;      // [16] values wave 0 publishes to the other waves
@@ -165,8 +164,7 @@ __device__ Lds carve(char* base, const SearchParams& p) {
   s.q = (float*)take(sizeof(float) * p.q_lds_floats);
   s.rk = (float*)take(sizeof(float) * rerank_slots(p));
   s.lut = (float*)take(sizeof(float) * (p.mode == MODE_PQ ? p.pq_m * 256 : 0));
-  s.hkey = (uint32_t*)take(sizeof(uint32_t) * (p.mode == MODE_SPARSE ? kHashSlots : 0));
-  s.hval = (float*)take(sizeof(float) * (p.mode == MODE_SPARSE ? kHashSlots : 0));
+  s.htab = (uint2*)take(sizeof(uint2) * (p.mode == MODE_SPARSE ? kHashSlots : 0));
   s.sb = (int64_t*)take(sizeof(int64_t) * (p.mode == MODE_SPARSE ? 64 : 0));
   s.se = (int64_t*)take(sizeof(int64_t) * (p.mode == MODE_SPARSE ? 64 : 0));
   s.ctl = (int32_t*)take(sizeof(int32_t) * 16);
@@ -462,7 +460,7 @@ __device__ __forceinline__ uint32_t hash_slot(uint32_t t) {
 
 struct Sparse {
   __device__ __forceinline__ bool prep(const SearchParams& p, const Lds& s, int64_t q) {
-    for (int i = threadIdx.x; i < kHashSlots; i += blockDim.x) { s.hkey[i] = kHashEmpty; s.hval[i] = 0.0f; }
+    for (int i = threadIdx.x; i < kHashSlots; i += blockDim.x) s.htab[i] = make_uint2(kHashEmpty, 0u);
     __syncthreads();
     const int64_t b = p.q_ptr[q];
     int64_t e = p.q_ptr[q + 1];
@@ -473,8 +471,8 @@ struct Sparse {
       const float w = p.q_vals[j];
       uint32_t h = hash_slot(t);
       while (true) {
-        const uint32_t prev = atomicCAS(&s.hkey[h], kHashEmpty, t);
-        if (prev == kHashEmpty || prev == t) { s.hval[h] = w; break; }
+        const uint32_t prev = atomicCAS(&s.htab[h].x, kHashEmpty, t);
+        if (prev == kHashEmpty || prev == t) { s.htab[h].y = __float_as_uint(w); break; }
         h = (h + 1) & (kHashSlots - 1);
       }
     }
@@ -482,13 +480,14 @@ struct Sparse {
     return ok;
   }
 
-  __device__ __forceinline__ float weight(const Lds& s, uint32_t t) const {
-    uint32_t h = hash_slot(t);
+  // The weight of term t when its first probe, slot h, held another term:
+  // the probe walks on to t or to an empty slot (0: t is not in the query).
+  __device__ __forceinline__ float weight_after(const Lds& s, uint32_t t, uint32_t h) const {
     while (true) {
-      const uint32_t k = s.hkey[h];
-      if (k == t) return s.hval[h];
-      if (k == kHashEmpty) return 0.0f;
       h = (h + 1) & (kHashSlots - 1);
+      const uint2 e = s.htab[h];
+      if (e.x == t) return __uint_as_float(e.y);
+      if (e.x == kHashEmpty) return 0.0f;
     }
   }
 
@@ -531,9 +530,22 @@ struct Sparse {
           tid[u] = (uint32_t)p.sp_ids[jc];
           val[u] = p.sp_vals[jc];
         }
+        // the first probe of every document's term at once (one LDS wait,
+        // not one per document); only a collision walks on
+        uint32_t hs[U];
+        uint2 ent[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          hs[u] = hash_slot(tid[u]);
+          ent[u] = s.htab[hs[u]];
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-          if (b[u] + off < e[u]) acc[u] = __builtin_fmaf(weight(s, tid[u]), val[u], acc[u]);
+          if (b[u] + off < e[u]) {
+            float w = ent[u].x == tid[u] ? __uint_as_float(ent[u].y) : 0.0f;
+            if (ent[u].x != tid[u] && ent[u].x != kHashEmpty) w = weight_after(s, tid[u], hs[u]);
+            acc[u] = __builtin_fmaf(w, val[u], acc[u]);
+          }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
