@@ -646,16 +646,17 @@ __device__ __forceinline__ int merge_sorted(float* dkey, uint32_t* did, int w, i
       float ok[E];
       uint32_t oi[E];
       int a[E + 1];
+      // read unconditionally (entry w - 1 past the end; those values are
+      // not used), so that the reads are waited for together, not one by one
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        ok[e] = 0.0f;
-        oi[e] = 0u;
-        if (jb + e < w) { ok[e] = dkey[jb + e]; oi[e] = did[jb + e]; }
+        const int jj = jb + e < w ? jb + e : w - 1;
+        ok[e] = dkey[jj];
+        oi[e] = did[jj];
       }
-      float nk = 0.0f;
-      uint32_t ni = 0u;
       const bool has_next = jb + E < w;
-      if (has_next) { nk = dkey[jb + E]; ni = did[jb + E] & kIdMask; }
+      const float nk = dkey[has_next ? jb + E : w - 1];
+      const uint32_t ni = did[has_next ? jb + E : w - 1] & kIdMask;
       // a[e]: new entries below old entry jb + e; a[E]: below the entry after the block
       int c = jb < w ? count_below(nkey, nid, mnew, ok[0], oi[0] & kIdMask) : 0;
       a[0] = c;
@@ -1143,14 +1144,12 @@ __device__ __forceinline__ void run_query(const SearchParams& p, const Lds& s, P
       const bool full = w + wb >= ef;
       const float tk = hd.tk;
       const uint32_t ti = hd.ti;
-      float kk = __builtin_inff();
-      uint32_t ki = kIdMask;
-      bool keep = false;
-      if (lane < m) {
-        kk = s.ckey[lane];
-        ki = (uint32_t)s.cid[lane];
-        keep = !full || kid_lt(kk, ki, tk, ti);
-      }
+      // (read for every lane, entry 0 past m, so that both reads are waited
+      // for together)
+      float kk = s.ckey[lane < m ? lane : 0];
+      uint32_t ki = (uint32_t)s.cid[lane < m ? lane : 0];
+      if (lane >= m) { kk = __builtin_inff(); ki = kIdMask; }
+      const bool keep = lane < m && (!full || kid_lt(kk, ki, tk, ti));
       const uint64_t km = ballot(keep);
       const int mnew = __builtin_popcountll(km);
       // sorted order of the kept entries: each counts the kept entries below
